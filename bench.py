@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q19 stream-and-collide hot path on one MI355X.
+
+Workload (default): the 128^3 simple-cubic cell with one centred sphere of
+diameter 100 lattice units, D3Q19 TRT (Lambda = 3/16, tau = 0.8) with CLI
+interpolated bounce-back and the periodic pressure drop, FP32 storage of the
+deviations f - w, FP64 mean-velocity reductions every 100 steps.  One bench
+step is one time step of that production loop.  Inputs are synthetic and
+seeded; all state is resident in HBM when timing starts.
+
+Prints one JSON line: metric, value (fluid-cell updates per second, in
+millions), the roofline of the step kernel measured with HIP events on the
+stream it runs on, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 TRT MLUPS + %HBM roofline; time-to-steady-state (plain vs warm-start)"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1508_02960_amd", "csrc", "kernels.hpp")
+
+WORKLOADS = {
+    # name: (shape, sphere diameter, collision, wall, storage, tau, magic, delta_rho)
+    "sc128_d100_trt_cli_fp32": ((128, 128, 128), 100.0, "trt", "cli", "fp32", 0.8, 3 / 16, 1.5e-4),
+    "sc256_d200_trt_cli_fp32": ((256, 256, 256), 200.0, "trt", "cli", "fp32", 0.8, 3 / 16, 1.5e-4),
+    "sc32_d24_trt_sbb_fp64": ((32, 32, 32), 24.0, "trt", "sbb", "fp64", 0.8, 3 / 16, 2.15e-6),
+}
+DEFAULT_WORKLOAD = "sc128_d100_trt_cli_fp32"
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(workload: str, n_fluid: int):
+    """HBM bytes per step-kernel launch from committed rocprofv3 counters, or
+    None if they were taken on a different kernel source or workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s: float):
+    """The FP64 CPU oracle on the same workload, single thread, for as many
+    whole steps as fit in about budget_s seconds (at least one)."""
+    import oracle
+
+    oracle.build(force=False)
+    shape, dia, coll, wall, _, tau, magic, drho = wl
+    from paper_1508_02960_amd import inputs
+
+    o = oracle.Oracle(shape, tau=tau, magic=magic, delta_rho=drho, collision=coll, wall=wall,
+                      spheres=inputs.centred_sphere(shape, dia))
+    o.init()
+    n_fluid = int((o.mask == 0).sum())
+    t0 = time.perf_counter()
+    o.step(1)
+    per = time.perf_counter() - t0
+    n_more = max(0, int(budget_s / max(per, 1e-9)) - 1)
+    t1 = time.perf_counter()
+    if n_more:
+        o.step(n_more)
+    total = per + (time.perf_counter() - t1)
+    steps = 1 + n_more
+    return {"value": round(n_fluid * steps / total / 1e6, 4), "unit": "MFLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the same workload ({shape[2]}x{shape[1]}x"
+                      f"{shape[0]}, {n_fluid} fluid cells), single thread, {total:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of CPU oracle time for the cpu_baseline sample (0: skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1508_02960_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    wl = WORKLOADS[args.workload]
+    shape, dia, coll, wall, storage, tau, magic, drho = wl
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d = lbm.Domain(shape, tau=tau, magic=magic, delta_rho=drho, collision=coll, wall=wall,
+                   storage=storage, spheres=inputs.centred_sphere(shape, dia), device=dev,
+                   check_interval=100)
+    n_fluid, n_cells = d.n_fluid, d.ncell
+    stream = d.stream
+    print(f"[bench] workload {args.workload}: {n_cells} cells, {n_fluid} fluid, "
+          f"{d.info.n_links} links, workspace {d.info.workspace_bytes / 2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+
+    # warm-up (also develops a non-trivial flow)
+    d.step(args.warmup)
+    d.synchronize()
+
+    # timed region: K steps of the production loop (residual check every 100 steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    status, done, res = d.run_to_residual(0.0, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    loop_ms = e0.elapsed_time(e1)
+    assert done == args.steps, (status, done)
+    U, vmax, _ = d.mean_velocity()
+    if not np.isfinite(U[0]):
+        print("[bench] non-finite state", file=sys.stderr)
+        return 1
+
+    # step-kernel timing: back-to-back launches bracketed by events on the
+    # library's stream
+    k_steps = max(args.steps, 200)
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    d.step(k_steps)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kernel_ms = k0.elapsed_time(k1) / k_steps
+
+    ms_per_step = max(loop_ms, wall_s * 1e3) / args.steps
+    value = n_fluid / (ms_per_step * 1e-3) / 1e6
+    bpu = int(d.info.bytes_per_fluid_update)
+    alg_bytes = n_fluid * bpu
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, n_fluid)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if storage == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "grid": list(shape[::-1]),
+            "sphere_diameter": dia,
+            "collision": coll, "wall": wall, "storage": storage,
+            "tau": tau, "magic": magic, "delta_rho": drho,
+            "fluid_cells": n_fluid, "cells": n_cells,
+            "mlups_all_cells": round(n_cells / (ms_per_step * 1e-3) / 1e6, 2),
+            "check_interval": 100,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "step_kernel",
+            "kernel_ms": round(kernel_ms, 6),
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "bytes_per_fluid_update": bpu,
+        },
+    }
+    d.close()
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

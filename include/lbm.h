@@ -1,0 +1,190 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann hot path for
+ * pore-scale flow through sphere packs, after Fattahi et al., "Pore-scale
+ * lattice Boltzmann simulation of laminar and turbulent flow through a
+ * sphere pack" (arXiv:1508.02960).
+ *
+ * One library, liblbm.so.  Every entry point returns an lbm_status; nothing
+ * throws across the ABI.  A domain is created on the host (geometry, wall
+ * links and wall distances are computed once, Sec. 3: "we compute the
+ * wall-distances ... only once before the time-stepping loop"), then bound to
+ * a caller-owned device workspace and a HIP stream.  The library never
+ * allocates device memory: the caller (for instance a torch.uint8 tensor on
+ * the GPU) owns the workspace and must keep it alive until lbm_destroy.
+ *
+ * Lattice and layout (shared with the tests; the order of the 19 velocities
+ * is an interface convention):
+ *   k  = 0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
+ *        6:(0,0,-1) 7:(1,1,0) 8:(-1,1,0) 9:(1,-1,0) 10:(-1,-1,0) 11:(1,0,1)
+ *        12:(-1,0,1) 13:(1,0,-1) 14:(-1,0,-1) 15:(0,1,1) 16:(0,-1,1)
+ *        17:(0,1,-1) 18:(0,-1,-1)
+ *   cell c = x + nx*(y + ny*z); node (x,y,z) sits at position (x,y,z).
+ *   Host-side population arrays are double g[k*ncell + c] holding the
+ *   deviation g_k = f_k - w_k of the post-collision state (w = 1/3, 1/18,
+ *   1/36); entries of solid cells are 0.
+ *   The box is periodic in x, y and z.  The pressure drop acts along +x
+ *   (Sec. 2.2.2): rho_left = rho_right + delta_rho across the x-periodic plane.
+ *
+ * Threading: calls on one domain must not overlap.  Different domains are
+ * independent.  All device work is enqueued on the domain's stream; calls that
+ * return host data synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_domain_s* lbm_domain;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = 1,   /* bad parameter, pointer or size; nothing changed */
+  LBM_ERR_WORKSPACE = 2,     /* workspace missing or smaller than required      */
+  LBM_ERR_DEVICE = 3,        /* a HIP call failed (message in lbm_last_error)   */
+  LBM_ERR_UNSTABLE = 4,      /* non-finite state or |u| above the sound speed   */
+  LBM_ERR_NOT_CONVERGED = 5, /* max_steps reached before the residual test held */
+  LBM_ERR_STATE = 6          /* call not valid in the current state             */
+} lbm_status;
+
+/* Collision operator, Sec. 2.1: eq. (SRT) with R = omega I, eq. (TRT), eq. (MRT). */
+typedef enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 } lbm_collision;
+
+/* Solid-wall rule, Sec. 2.2.1: eq. (noslip) simple bounce-back or eq. (CLI)
+ * central linear interpolation with the wall distance q of each link. */
+typedef enum { LBM_WALL_SBB = 0, LBM_WALL_CLI = 1 } lbm_wall;
+
+/* Storage precision of the populations (deviations g = f - w).  FP64 computes
+ * in double, FP32 in float. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1 } lbm_storage;
+
+/* A sphere in lattice units; spheres and their periodic images may overlap.
+ * Radii must be positive and smaller than the smallest box edge. */
+typedef struct {
+  double cx, cy, cz, r;
+} lbm_sphere;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* box edge in cells, each >= 1, nx*ny*nz < 2^31      */
+  double tau;             /* relaxation time 1/omega+, > 1/2; nu = (tau-1/2)/3  */
+  double magic;           /* TRT Lambda in (0, 3/4] (Sec. 2.1); unused by SRT/MRT */
+  double delta_rho;       /* density jump across the x-periodic plane           */
+  int32_t collision;      /* lbm_collision                                      */
+  int32_t wall;           /* lbm_wall                                           */
+  int32_t storage;        /* lbm_storage                                        */
+  int32_t check_interval; /* steps between residual checks (0 => 100)           */
+} lbm_params;
+
+typedef struct {
+  int64_t n_cells;         /* nx*ny*nz                                          */
+  int64_t n_fluid;         /* fluid cells                                       */
+  int64_t n_links;         /* wall links (fluid cell, direction into solid)     */
+  int64_t n_fallback;      /* links whose second fluid node is solid (CLI->SBB) */
+  int64_t workspace_bytes; /* device bytes lbm_bind needs                       */
+  int64_t plane_stride;    /* elements between direction planes on the device   */
+  double nu;               /* kinematic viscosity (tau - 1/2)/3                 */
+  double omega_plus;       /* 1/tau                                             */
+  double omega_minus;      /* TRT antisymmetric rate from Lambda                */
+  int64_t bytes_per_fluid_update; /* algorithmic HBM bytes per fluid-cell update */
+} lbm_info;
+
+/* Create a domain on the host (no device work).  Sec. 3 / Sec. 2.2.1.
+ *   solid_mask : host uint8[nz*ny*nx], 1 = solid, or NULL when spheres given.
+ *                With a mask every wall link gets q = 1/2 (CLI == SBB).
+ *   spheres    : host array of n_spheres spheres, or NULL/0 with a mask.  A
+ *                node is solid iff it lies strictly inside a sphere or one of
+ *                its periodic images; q of a link is where the segment from the
+ *                fluid node along e_j first meets a sphere surface, in [0,1].
+ *   Exactly one of solid_mask and spheres must be given.  Inputs are copied;
+ *   the caller may free them after the call.
+ * Errors: LBM_ERR_INVALID_ARG for tau <= 1/2, TRT Lambda outside (0, 3/4],
+ * non-positive or too large dimensions, no fluid cell, bad sphere radius,
+ * unknown enum values, both or neither geometry source.  *out is then NULL. */
+lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere* spheres,
+                             int32_t n_spheres, const lbm_params* params,
+                             lbm_domain* out);
+
+/* Sizes and derived constants of a created domain. */
+lbm_status lbm_get_info(lbm_domain d, lbm_info* info);
+
+/* Copy the solid mask (uint8[ncell]) to host memory. */
+lbm_status lbm_get_mask(lbm_domain d, uint8_t* mask);
+
+/* Copy the wall links to host memory, n_links entries each, sorted by cell
+ * then direction: fluid cell index, direction j (1..18) with c + e_j solid,
+ * wall distance q (Sec. 2.2.1), and 1 if c - e_j is solid (CLI falls back to
+ * bounce-back).  Any pointer may be NULL to skip that array. */
+lbm_status lbm_get_links(lbm_domain d, int64_t* cell, int32_t* dir, double* q,
+                         uint8_t* fallback);
+
+/* Bind the device workspace and stream, upload geometry, and initialise the
+ * fluid at rest (g = 0).  workspace: device pointer, 256-byte aligned, at least
+ * info.workspace_bytes; owned by the caller.  stream: a hipStream_t or NULL for
+ * the null stream.  May be called again to re-bind (state is re-initialised). */
+lbm_status lbm_bind(lbm_domain d, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Set the state to the equilibrium g^eq(drho0, u0) of eq. (equilibrium) on
+ * fluid cells.  drho0: host double[ncell] or NULL (0); u0: host
+ * double[3*ncell] component-major (u_x block, u_y block, u_z block) or NULL. */
+lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const double* u0);
+
+/* Load / read back the full post-collision state (host double[19*ncell],
+ * layout above).  Values of solid cells are ignored on load, 0 on read. */
+lbm_status lbm_set_state(lbm_domain d, const double* g);
+lbm_status lbm_get_state(lbm_domain d, double* g);
+
+/* Enqueue n fused stream-then-collide steps (Sec. 2, eq. (streaming) then
+ * eq. (collision)) with the wall rule and the periodic pressure drop.
+ * Asynchronous; n = 0 is a no-op. */
+lbm_status lbm_step(lbm_domain d, int64_t n);
+
+/* Step until the relative change of the superficial mean velocity U_x over
+ * check_interval steps stays below tol for three checks in a row (stopping
+ * rule read from Sec. 4).  Returns LBM_OK when converged,
+ * LBM_ERR_NOT_CONVERGED at max_steps, LBM_ERR_UNSTABLE on a non-finite state
+ * or a speed above 1/sqrt(3) (the domain then rejects lbm_step with
+ * LBM_ERR_STATE until re-initialised).  steps_done/residual may be NULL. */
+lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_steps,
+                               int64_t* steps_done, double* residual);
+
+/* Density deviation (host double[ncell]) and velocity (host double[3*ncell],
+ * component-major) of the current state, eq. (Macro); 0 on solid cells.
+ * Either pointer may be NULL. */
+lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u);
+
+/* Superficial mean velocity U[3] = sum over fluid cells of u / ncell, the
+ * largest |u| over fluid cells and the total density deviation, reduced in
+ * double precision on the device.  Any pointer may be NULL. */
+lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
+                             double* total_drho);
+
+/* Darcy permeability, eq. (Darcy): K_D = nu U_x nx / dp with dp = delta_rho/3;
+ * U is the superficial velocity.  Requires delta_rho != 0. */
+lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x);
+
+/* Momentum-exchange force on the solid (host double[3]): sum over wall links
+ * (c, j) of e_j (f~_j(c, t) + f_kbar(c, t+1)), f = g + w, with the incoming
+ * value given by the wall rule. */
+lbm_status lbm_drag(lbm_domain d, double F[3]);
+
+/* Change the pressure drop of a bound domain (state kept). */
+lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho);
+
+/* Wait for the domain's stream. */
+lbm_status lbm_synchronize(lbm_domain d);
+
+/* Release host memory of the domain (the workspace stays the caller's). */
+lbm_status lbm_destroy(lbm_domain d);
+
+const char* lbm_status_string(lbm_status s);
+/* Last error message of the domain ("" if none); NULL domain: last create error. */
+const char* lbm_last_error(lbm_domain d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

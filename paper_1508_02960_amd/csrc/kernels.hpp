@@ -1,0 +1,460 @@
+// HIP kernels of the D3Q19 hot path for gfx950 (MI355X).
+//
+// Data layout in HBM: two population buffers (A: current post-collision
+// state, B: next), each 19 direction planes of `stride` elements, the plane
+// of direction k holding g_k = f_k - w_k for every cell c = x + nx*(y + ny*z).
+// A uint32 flag word per cell marks solid cells and the directions whose pull
+// source is solid.  For such a wall link the otherwise unused slot of the
+// solid source node in plane k holds the CLI coefficient a = (1-2q)/(1+2q)
+// (0 for fallback links), written once at bind time into both buffers; solid
+// cells are never written by the step, so the slots persist.
+//
+// The step is a pull scheme: each fluid cell gathers its 19 incoming values
+// from its neighbours (one read per element of A), applies the wall rule and
+// the periodic pressure jump, collides, and writes its 19 values to B (one
+// aligned write per element).  It is HBM-bandwidth bound.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum { kSRT = 0, kTRT = 1, kMRT = 2 };
+enum { kSBB = 0, kCLI = 1 };
+
+struct StepParams {
+  int nx, ny, nz;
+  long long stride;   // elements between direction planes
+  double jump_axis;   // w_axis * delta_rho
+  double jump_diag;   // w_diag * delta_rho
+  double omega_p;     // 1/tau (SRT, TRT symmetric, MRT viscous modes)
+  double omega_m;     // TRT antisymmetric rate
+  double s_e;         // MRT energy modes 1, 2
+  double s_zeta;      // MRT remaining kinetic modes
+};
+
+template <typename S>
+struct ComputeOf {
+  using type = float;
+};
+template <>
+struct ComputeOf<double> {
+  using type = double;
+};
+
+// ---------------------------------------------------------------- collision
+// Input: post-streaming deviations g[19]; output overwrites g.
+
+template <typename C>
+__device__ __forceinline__ void moments(const C* g, C& rho, C& ux, C& uy, C& uz) {
+  rho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) +
+        ((g[8] + g[9]) + (g[10] + g[11])) + ((g[12] + g[13]) + (g[14] + g[15])) +
+        ((g[16] + g[17]) + g[18]);
+  ux = ((g[1] - g[2]) + (g[7] - g[10])) + ((g[9] - g[8]) + (g[11] - g[14])) + (g[13] - g[12]);
+  uy = ((g[3] - g[4]) + (g[7] - g[10])) + ((g[8] - g[9]) + (g[15] - g[18])) + (g[17] - g[16]);
+  uz = ((g[5] - g[6]) + (g[11] - g[14])) + ((g[12] - g[13]) + (g[15] - g[18])) + (g[16] - g[17]);
+}
+
+// Deviation equilibrium w_k {drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u}.
+template <typename C, int K>
+__device__ __forceinline__ C geq(C rho, C ux, C uy, C uz, C usq) {
+  constexpr C w = (C)kLat.w[K];
+  const C eu = (C)kLat.ex[K] * ux + (C)kLat.ey[K] * uy + (C)kLat.ez[K] * uz;
+  return w * (rho + (C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * usq);
+}
+
+template <typename C>
+__device__ __forceinline__ void collide_srt(C* g, C omega) {
+  C rho, ux, uy, uz;
+  moments(g, rho, ux, uy, uz);
+  const C usq = ux * ux + uy * uy + uz * uz;
+#define LBM_SRT(K) g[K] = g[K] - omega * (g[K] - geq<C, K>(rho, ux, uy, uz, usq));
+  LBM_SRT(0) LBM_SRT(1) LBM_SRT(2) LBM_SRT(3) LBM_SRT(4) LBM_SRT(5) LBM_SRT(6) LBM_SRT(7)
+  LBM_SRT(8) LBM_SRT(9) LBM_SRT(10) LBM_SRT(11) LBM_SRT(12) LBM_SRT(13) LBM_SRT(14)
+  LBM_SRT(15) LBM_SRT(16) LBM_SRT(17) LBM_SRT(18)
+#undef LBM_SRT
+}
+
+// TRT (eq. (TRT)): symmetric part relaxed with omega+, antisymmetric with
+// omega-, per opposite pair (k, kb).
+template <typename C, int K, int KB>
+__device__ __forceinline__ void trt_pair(C* g, C rho, C ux, C uy, C uz, C usq, C wp, C wm) {
+  constexpr C w = (C)kLat.w[K];
+  const C eu = (C)kLat.ex[K] * ux + (C)kLat.ey[K] * uy + (C)kLat.ez[K] * uz;
+  const C eq_p = w * (rho + (C)4.5 * eu * eu - (C)1.5 * usq);
+  const C eq_m = w * (C)3 * eu;
+  const C dp = wp * ((C)0.5 * (g[K] + g[KB]) - eq_p);
+  const C dm = wm * ((C)0.5 * (g[K] - g[KB]) - eq_m);
+  g[K] = g[K] - dp - dm;
+  g[KB] = g[KB] - dp + dm;
+}
+
+template <typename C>
+__device__ __forceinline__ void collide_trt(C* g, C wp, C wm) {
+  C rho, ux, uy, uz;
+  moments(g, rho, ux, uy, uz);
+  const C usq = ux * ux + uy * uy + uz * uz;
+  g[0] = g[0] - wp * (g[0] - (C)kLat.w[0] * (rho - (C)1.5 * usq));
+  trt_pair<C, 1, 2>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 3, 4>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 5, 6>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 7, 10>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 8, 9>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 11, 14>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 12, 13>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 15, 18>(g, rho, ux, uy, uz, usq, wp, wm);
+  trt_pair<C, 16, 17>(g, rho, ux, uy, uz, usq, wp, wm);
+}
+
+// MRT (eq. (MRT)) as g* = g - M^-1 S M (g - g^eq) with M^-1 = M^T diag(1/|M_i|^2).
+// M is a compile-time constant; the unrolled products fold its zeros.
+// Conserved moments (rows 0, 3, 5, 7) carry no non-equilibrium part.
+template <typename C>
+__device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
+  C rho, ux, uy, uz;
+  moments(g, rho, ux, uy, uz);
+  const C usq = ux * ux + uy * uy + uz * uz;
+  C d[kQ];
+  d[0] = g[0] - geq<C, 0>(rho, ux, uy, uz, usq);
+#define LBM_D(K) d[K] = g[K] - geq<C, K>(rho, ux, uy, uz, usq);
+  LBM_D(1) LBM_D(2) LBM_D(3) LBM_D(4) LBM_D(5) LBM_D(6) LBM_D(7) LBM_D(8) LBM_D(9)
+  LBM_D(10) LBM_D(11) LBM_D(12) LBM_D(13) LBM_D(14) LBM_D(15) LBM_D(16) LBM_D(17) LBM_D(18)
+#undef LBM_D
+  C r[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    if (i == 0 || i == 3 || i == 5 || i == 7) {
+      r[i] = (C)0;
+      continue;
+    }
+    C m = (C)0;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      if (kMrt.m[i][k] != 0.0) m += (C)kMrt.m[i][k] * d[k];
+    }
+    const C s = (i == 1 || i == 2) ? s_e
+                : (i == 9 || i == 11 || i == 13 || i == 14 || i == 15) ? s_nu
+                                                                     : s_zeta;
+    r[i] = s * m * (C)(1.0 / kMrt.n2[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) {
+    C a = (C)0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      if (i == 0 || i == 3 || i == 5 || i == 7) continue;
+      if (kMrt.m[i][k] != 0.0) a += (C)kMrt.m[i][k] * r[i];
+    }
+    g[k] = g[k] - a;
+  }
+}
+
+// ---------------------------------------------------------------- the step
+
+// Flat cell index of the node at (x + dx, y + dy, z + dz) given the wrapped
+// neighbour coordinates of the thread's node.
+struct Nbr {
+  int xs[3];  // x - 1, x, x + 1 (wrapped)
+  int ys[3];  // row offsets of y - 1, y, y + 1 (wrapped) times nx
+  int zs[3];  // plane offsets of z - 1, z, z + 1 (wrapped) times nx*ny
+  __device__ __forceinline__ int at(int dx, int dy, int dz) const {
+    return xs[dx + 1] + ys[dy + 1] + zs[dz + 1];
+  }
+};
+
+template <typename S, int COLL, int WALL>
+__global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
+                                                   S* __restrict__ dst,
+                                                   const uint32_t* __restrict__ flags,
+                                                   const StepParams p) {
+  using C = typename ComputeOf<S>::type;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= p.nx || y >= p.ny) return;
+  const int nx = p.nx, plane = p.nx * p.ny;
+  const int c = x + nx * y + plane * z;
+  const uint32_t fl = flags[c];
+  if (fl & kSolid) return;
+
+  Nbr n;
+  n.xs[0] = x == 0 ? nx - 1 : x - 1;
+  n.xs[1] = x;
+  n.xs[2] = x == nx - 1 ? 0 : x + 1;
+  n.ys[0] = (y == 0 ? p.ny - 1 : y - 1) * nx;
+  n.ys[1] = y * nx;
+  n.ys[2] = (y == p.ny - 1 ? 0 : y + 1) * nx;
+  n.zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
+  n.zs[1] = z * plane;
+  n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
+
+  const long long st = p.stride;
+  C g[kQ];
+  // pull: direction k arrives from x - e_k
+#pragma unroll
+  for (int k = 0; k < kQ; ++k)
+    g[k] = (C)src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])];
+
+  // wall links: the pulled value is the stored coefficient a
+  if (fl & kLinkMask) {
+#pragma unroll
+    for (int k = 1; k < kQ; ++k) {
+      if (fl & (1u << k)) {
+        const int j = kLat.opp[k];
+        const C own_j = (C)src[j * st + c];
+        if constexpr (WALL == kCLI) {
+          const C a = g[k];
+          const C own_k = (C)src[k * st + c];
+          // second node x_f2 = x + e_k (away from the wall), read across the
+          // x-periodic plane with the pressure jump
+          C far_j = (C)src[j * st + n.at(kLat.ex[k], kLat.ey[k], kLat.ez[k])];
+          if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
+          if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
+          g[k] = a * far_j - a * own_k + own_j;
+        } else {
+          g[k] = own_j;
+        }
+      }
+    }
+  }
+
+  // periodic pressure drop on pulls across the x-plane (not on wall links)
+  if (x == 0) {
+    const C ja = (C)p.jump_axis, jd = (C)p.jump_diag;
+    if (!(fl & (1u << 1))) g[1] += ja;
+    if (!(fl & (1u << 7))) g[7] += jd;
+    if (!(fl & (1u << 9))) g[9] += jd;
+    if (!(fl & (1u << 11))) g[11] += jd;
+    if (!(fl & (1u << 13))) g[13] += jd;
+  }
+  if (x == nx - 1) {
+    const C ja = (C)p.jump_axis, jd = (C)p.jump_diag;
+    if (!(fl & (1u << 2))) g[2] -= ja;
+    if (!(fl & (1u << 8))) g[8] -= jd;
+    if (!(fl & (1u << 10))) g[10] -= jd;
+    if (!(fl & (1u << 12))) g[12] -= jd;
+    if (!(fl & (1u << 14))) g[14] -= jd;
+  }
+
+  if constexpr (COLL == kSRT) {
+    collide_srt<C>(g, (C)p.omega_p);
+  } else if constexpr (COLL == kTRT) {
+    collide_trt<C>(g, (C)p.omega_p, (C)p.omega_m);
+  } else {
+    collide_mrt<C>(g, (C)p.omega_p, (C)p.s_e, (C)p.s_zeta);
+  }
+
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) dst[k * st + c] = (S)g[k];
+}
+
+// ------------------------------------------------------------ reductions
+// FP64 sums over fluid cells of the stored state: [0..2] sum u, [3] sum drho,
+// [4] max |u|^2, [5] count of non-finite cells.  Deterministic: fixed grid,
+// fixed per-thread order, fixed tree.
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+constexpr int kRedVals = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Block reduction of kRedVals doubles; kinds: 0 = sum, 1 = max.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&kind)[NV], double* out) {
+  __shared__ double sh[kRedThreads / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = kind[i] ? wave_max(v[i]) : wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[wv][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    double a = sh[0][i];
+    for (int w = 1; w < kRedThreads / 64; ++w) a = kind[i] ? fmax(a, sh[w][i]) : a + sh[w][i];
+    out[i] = a;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __restrict__ src,
+                                                                   const uint32_t* __restrict__ flags,
+                                                                   long long stride, int ncell,
+                                                                   double* __restrict__ partials) {
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long c = blockIdx.x * kRedThreads + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * kRedThreads) {
+    if (flags[c] & kSolid) continue;
+    double g[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) g[k] = (double)src[k * stride + c];
+    double rho, ux, uy, uz;
+    moments<double>(g, rho, ux, uy, uz);
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    v[0] += ux;
+    v[1] += uy;
+    v[2] += uz;
+    v[3] += rho;
+    if (isfinite(u2) && isfinite(rho)) {
+      v[4] = fmax(v[4], u2);
+    } else {
+      v[5] += 1.0;
+    }
+  }
+  const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
+  block_reduce<kRedVals>(v, kind, partials + blockIdx.x * kRedVals);
+}
+
+// Momentum-exchange force over the wall links (f = g + w), same wall rule as
+// the step kernel.
+template <typename S, int WALL>
+__global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__ src,
+                                                           const uint32_t* __restrict__ flags,
+                                                           const StepParams p,
+                                                           double* __restrict__ partials) {
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int ncell = p.nx * p.ny * p.nz;
+  const long long st = p.stride;
+  for (long long cc = blockIdx.x * kRedThreads + threadIdx.x; cc < ncell;
+       cc += (long long)gridDim.x * kRedThreads) {
+    const int c = (int)cc;
+    const uint32_t fl = flags[c];
+    if ((fl & kSolid) || !(fl & kLinkMask)) continue;
+    const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / (p.nx * p.ny);
+    for (int k = 1; k < kQ; ++k) {
+      if (!(fl & (1u << k))) continue;
+      const int j = kLat.opp[k];
+      const double own_j = (double)src[j * st + c];
+      double back = own_j;
+      if (WALL == kCLI) {
+        const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
+                  sz = (z - kLat.ez[k] + p.nz) % p.nz;
+        const double a = (double)src[k * st + sx + p.nx * (sy + p.ny * sz)];
+        const int tx = x + kLat.ex[k];
+        const int fx = (tx + p.nx) % p.nx, fy = (y + kLat.ey[k] + p.ny) % p.ny,
+                  fz = (z + kLat.ez[k] + p.nz) % p.nz;
+        double far_j = (double)src[j * st + fx + p.nx * (fy + p.ny * fz)];
+        const double jw = kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag;
+        if (tx >= p.nx) far_j -= jw;
+        if (tx < 0) far_j += jw;
+        back = a * far_j - a * (double)src[k * st + c] + own_j;
+      }
+      const double tot = (own_j + kLat.w[j]) + (back + kLat.w[k]);
+      v[0] += kLat.ex[j] * tot;
+      v[1] += kLat.ey[j] * tot;
+      v[2] += kLat.ez[j] * tot;
+    }
+  }
+  const int kind[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  block_reduce<kRedVals>(v, kind, partials + blockIdx.x * kRedVals);
+}
+
+// Second pass: one block folds the per-block partials in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(const double* __restrict__ partials,
+                                                                   int nblocks, int max_slot,
+                                                                   double* __restrict__ out) {
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int kind[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (max_slot >= 0) kind[max_slot] = 1;
+  for (int b = threadIdx.x; b < nblocks; b += kRedThreads)
+#pragma unroll
+    for (int i = 0; i < kRedVals; ++i)
+      v[i] = kind[i] ? fmax(v[i], partials[b * kRedVals + i]) : v[i] + partials[b * kRedVals + i];
+  block_reduce<kRedVals>(v, kind, out);
+}
+
+// ------------------------------------------------------------ state I/O
+
+template <typename S>
+__global__ void fill_kernel(S* __restrict__ buf, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    buf[i] = (S)0;
+}
+
+template <typename S>
+__global__ void scatter_kernel(S* __restrict__ a, S* __restrict__ b,
+                               const long long* __restrict__ slot,
+                               const double* __restrict__ value, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    a[slot[i]] = (S)value[i];
+    b[slot[i]] = (S)value[i];
+  }
+}
+
+// One direction plane, cells [c0, c0 + n), to/from a double staging buffer.
+template <typename S>
+__global__ void get_plane_kernel(const S* __restrict__ plane, const uint32_t* __restrict__ flags,
+                                 int c0, int n, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = (flags[c0 + i] & kSolid) ? 0.0 : (double)plane[c0 + i];
+}
+
+template <typename S>
+__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags, int c0,
+                                 int n, const double* __restrict__ in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!(flags[c0 + i] & kSolid)) plane[c0 + i] = (S)in[i];
+}
+
+// g = g^eq(drho, u) for fluid cells [c0, c0 + n); stage = drho | ux | uy | uz
+// blocks of n doubles (all-zero staging gives the rest state).
+template <typename S>
+__global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
+                               long long stride, int c0, int n, const double* __restrict__ stage) {
+  using C = typename ComputeOf<S>::type;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = c0 + i;
+  if (flags[c] & kSolid) return;
+  const C rho = (C)stage[i], ux = (C)stage[n + i], uy = (C)stage[2 * n + i],
+          uz = (C)stage[3 * n + i];
+  const C usq = ux * ux + uy * uy + uz * uz;
+  C g[kQ];
+#define LBM_EQ(K) g[K] = geq<C, K>(rho, ux, uy, uz, usq);
+  LBM_EQ(0) LBM_EQ(1) LBM_EQ(2) LBM_EQ(3) LBM_EQ(4) LBM_EQ(5) LBM_EQ(6) LBM_EQ(7) LBM_EQ(8)
+  LBM_EQ(9) LBM_EQ(10) LBM_EQ(11) LBM_EQ(12) LBM_EQ(13) LBM_EQ(14) LBM_EQ(15) LBM_EQ(16)
+  LBM_EQ(17) LBM_EQ(18)
+#undef LBM_EQ
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) buf[k * stride + c] = (S)g[k];
+}
+
+// drho, u of cells [c0, c0 + n) into stage (drho | ux | uy | uz blocks).
+template <typename S>
+__global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restrict__ flags,
+                             long long stride, int c0, int n, double* __restrict__ stage) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = c0 + i;
+  double rho = 0, ux = 0, uy = 0, uz = 0;
+  if (!(flags[c] & kSolid)) {
+    double g[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) g[k] = (double)buf[k * stride + c];
+    moments<double>(g, rho, ux, uy, uz);
+  }
+  stage[i] = rho;
+  stage[n + i] = ux;
+  stage[2 * n + i] = uy;
+  stage[3 * n + i] = uz;
+}
+
+}  // namespace lbm

@@ -1,0 +1,617 @@
+// C ABI of the D3Q19 hot path (include/lbm.h): domain lifetime, workspace
+// layout, kernel launches and host-side control of the time loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "geometry.hpp"
+#include "kernels.hpp"
+#include "lbm.h"
+
+#define LBM_API extern "C" __attribute__((visibility("default")))
+
+using namespace lbm;
+
+struct lbm_domain_s {
+  lbm_params p{};
+  Geometry geo;
+  std::string err;
+  // derived
+  long long stride = 0;  // elements per direction plane
+  size_t elem = 0;       // bytes per stored population
+  double nu = 0, omega_p = 0, omega_m = 0, s_e = 0, s_zeta = 0;
+  // device (inside the caller's workspace)
+  bool bound = false;
+  bool unstable = false;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;  // buf[cur] holds the current state
+  uint32_t* flags = nullptr;
+  long long* link_slot = nullptr;
+  double* link_coef = nullptr;
+  double* partials = nullptr;
+  double* result = nullptr;
+  double* stage = nullptr;
+  size_t stage_cells = 0;  // cells per staging chunk (4 doubles each)
+  // layout offsets
+  size_t off_buf[2] = {0, 0}, off_flags = 0, off_slot = 0, off_coef = 0, off_part = 0,
+         off_res = 0, off_stage = 0, total = 0;
+};
+
+namespace {
+
+std::string g_create_error;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+lbm_status fail(lbm_domain d, lbm_status s, const std::string& msg) {
+  if (d) d->err = msg;
+  return s;
+}
+
+#define HIP_OK(d, call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((d), LBM_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Direction planes are padded so that the 19 streams do not start on the same
+// HBM channel: round the cell count up to 1024 elements, plus 512 elements.
+long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
+
+void layout(lbm_domain d) {
+  const int64_t n = d->geo.ncell;
+  d->stride = plane_stride(n);
+  d->elem = d->p.storage == LBM_FP64 ? 8 : 4;
+  size_t o = 0;
+  const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
+  d->off_buf[0] = o;
+  o += bufb;
+  d->off_buf[1] = o;
+  o += bufb;
+  d->off_flags = o;
+  o += align256((size_t)n * 4);
+  const size_t nl = d->geo.link_cell.size();
+  d->off_slot = o;
+  o += align256(std::max<size_t>(nl, 1) * 8);
+  d->off_coef = o;
+  o += align256(std::max<size_t>(nl, 1) * 8);
+  d->off_part = o;
+  o += align256((size_t)kRedBlocks * kRedVals * 8);
+  d->off_res = o;
+  o += align256(kRedVals * 8);
+  // staging: at least one z-plane of cells, at least 1M cells, 4 doubles each
+  d->stage_cells = std::max<size_t>((size_t)d->geo.nx * d->geo.ny, size_t(1) << 20);
+  d->stage_cells = std::min<size_t>(d->stage_cells, (size_t)n);
+  d->off_stage = o;
+  o += align256(d->stage_cells * 4 * 8);
+  d->total = o;
+}
+
+template <typename S>
+void launch_step_t(lbm_domain d, const void* src, void* dst, const StepParams& sp) {
+  const int bx = std::min(512, ((d->geo.nx + 63) / 64) * 64);
+  const int by = std::max(1, 256 / bx);
+  dim3 block(bx, by, 1);
+  dim3 grid((d->geo.nx + bx - 1) / bx, (d->geo.ny + by - 1) / by, d->geo.nz);
+  const S* s = (const S*)src;
+  S* t = (S*)dst;
+  const int key = d->p.collision * 2 + d->p.wall;
+  switch (key) {
+    case 0: step_kernel<S, kSRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+    case 1: step_kernel<S, kSRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+    case 2: step_kernel<S, kTRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+    case 3: step_kernel<S, kTRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+    case 4: step_kernel<S, kMRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+    default: step_kernel<S, kMRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+  }
+}
+
+StepParams step_params(lbm_domain d) {
+  StepParams sp;
+  sp.nx = d->geo.nx;
+  sp.ny = d->geo.ny;
+  sp.nz = d->geo.nz;
+  sp.stride = d->stride;
+  sp.jump_axis = (1.0 / 18.0) * d->p.delta_rho;
+  sp.jump_diag = (1.0 / 36.0) * d->p.delta_rho;
+  sp.omega_p = d->omega_p;
+  sp.omega_m = d->omega_m;
+  sp.s_e = d->s_e;
+  sp.s_zeta = d->s_zeta;
+  return sp;
+}
+
+lbm_status enqueue_steps(lbm_domain d, int64_t n) {
+  const StepParams sp = step_params(d);
+  for (int64_t i = 0; i < n; ++i) {
+    const void* src = d->buf[d->cur];
+    void* dst = d->buf[1 - d->cur];
+    if (d->p.storage == LBM_FP64)
+      launch_step_t<double>(d, src, dst, sp);
+    else
+      launch_step_t<float>(d, src, dst, sp);
+    d->cur = 1 - d->cur;
+  }
+  HIP_OK(d, hipGetLastError());
+  return LBM_OK;
+}
+
+// Reduce the current state; vals (host, kRedVals doubles) after a stream sync.
+lbm_status reduce_state(lbm_domain d, double* vals) {
+  const int ncell = (int)d->geo.ncell;
+  if (d->p.storage == LBM_FP64)
+    reduce_state_kernel<double><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+        (const double*)d->buf[d->cur], d->flags, d->stride, ncell, d->partials);
+  else
+    reduce_state_kernel<float><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+        (const float*)d->buf[d->cur], d->flags, d->stride, ncell, d->partials);
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 4, d->result);
+  HIP_OK(d, hipGetLastError());
+  HIP_OK(d, hipMemcpyAsync(vals, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+lbm_status check_ready(lbm_domain d) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  if (!d->bound) return fail(d, LBM_ERR_STATE, "domain is not bound to a workspace");
+  return LBM_OK;
+}
+
+template <typename S>
+void launch_init(lbm_domain d, int c0, int n) {
+  const int bs = 256;
+  init_eq_kernel<S><<<(n + bs - 1) / bs, bs, 0, d->stream>>>((S*)d->buf[d->cur], d->flags,
+                                                                d->stride, c0, n, d->stage);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- creation
+
+LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere* spheres,
+                                     int32_t n_spheres, const lbm_params* params,
+                                     lbm_domain* out) {
+  g_create_error.clear();
+  if (!out) return LBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto bad = [](const std::string& m) {
+    g_create_error = m;
+    return LBM_ERR_INVALID_ARG;
+  };
+  if (!params) return bad("params is NULL");
+  const lbm_params& p = *params;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return bad("box edges must be >= 1");
+  const int64_t ncell = (int64_t)p.nx * p.ny * p.nz;
+  if (ncell >= (int64_t(1) << 31)) return bad("nx*ny*nz must be below 2^31");
+  if (p.ny > 65535 || p.nz > 65535) return bad("ny and nz must be at most 65535");
+  if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return bad("tau must be finite and > 1/2");
+  if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
+  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_CLI) return bad("unknown wall rule");
+  if (p.storage < LBM_FP64 || p.storage > LBM_FP32) return bad("unknown storage");
+  if (p.collision == LBM_TRT && !(p.magic > 0.0 && p.magic <= 0.75))
+    return bad("TRT magic parameter must lie in (0, 3/4]");
+  if (!std::isfinite(p.delta_rho)) return bad("delta_rho must be finite");
+  if (p.check_interval < 0) return bad("check_interval must be >= 0");
+  const bool has_mask = solid_mask != nullptr;
+  const bool has_spheres = spheres != nullptr && n_spheres > 0;
+  if (n_spheres < 0) return bad("n_spheres must be >= 0");
+  if (has_mask == has_spheres) return bad("give exactly one of solid_mask and spheres");
+  if (has_spheres) {
+    const double emin = std::min(p.nx, std::min(p.ny, p.nz));
+    for (int s = 0; s < n_spheres; ++s) {
+      const lbm_sphere& q = spheres[s];
+      if (!(q.r > 0.0) || !(q.r < emin)) return bad("sphere radius must lie in (0, min edge)");
+      if (!(q.cx >= 0 && q.cx < p.nx && q.cy >= 0 && q.cy < p.ny && q.cz >= 0 && q.cz < p.nz))
+        return bad("sphere centre must lie inside the box");
+    }
+  }
+  lbm_domain d = new (std::nothrow) lbm_domain_s();
+  if (!d) return bad("out of host memory");
+  d->p = p;
+  if (d->p.check_interval == 0) d->p.check_interval = 100;
+  std::string err;
+  try {
+    if (!build_geometry(solid_mask, spheres, has_spheres ? n_spheres : 0, p.nx, p.ny, p.nz,
+                        d->geo, err)) {
+      delete d;
+      return bad(err);
+    }
+  } catch (const std::bad_alloc&) {
+    delete d;
+    return bad("out of host memory building the geometry");
+  }
+  // Relaxation rates (Sec. 2.1): omega+ = 1/tau = (3 nu + 1/2)^-1; TRT
+  // omega- from Lambda = (1/omega+ - 1/2)(1/omega- - 1/2); MRT energy modes
+  // with (1/s_nu - 1/2)/(1/s_e - 1/2) = 4.6 and Pan's s_zeta = 8(2-s_nu)/(8-s_nu).
+  d->nu = (p.tau - 0.5) / 3.0;
+  d->omega_p = 1.0 / p.tau;
+  d->omega_m = p.collision == LBM_TRT ? 1.0 / (0.5 + p.magic / (p.tau - 0.5)) : d->omega_p;
+  d->s_e = 1.0 / (0.5 + (p.tau - 0.5) / 4.6);
+  d->s_zeta = 8.0 * (2.0 - d->omega_p) / (8.0 - d->omega_p);
+  layout(d);
+  *out = d;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_info(lbm_domain d, lbm_info* info) {
+  if (!d || !info) return LBM_ERR_INVALID_ARG;
+  info->n_cells = d->geo.ncell;
+  info->n_fluid = d->geo.n_fluid;
+  info->n_links = (int64_t)d->geo.link_cell.size();
+  info->n_fallback = d->geo.n_fallback;
+  info->workspace_bytes = (int64_t)d->total;
+  info->plane_stride = d->stride;
+  info->nu = d->nu;
+  info->omega_plus = d->omega_p;
+  info->omega_minus = d->omega_m;
+  info->bytes_per_fluid_update = (int64_t)(2 * kQ * d->elem);
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_mask(lbm_domain d, uint8_t* mask) {
+  if (!d || !mask) return LBM_ERR_INVALID_ARG;
+  std::memcpy(mask, d->geo.mask.data(), d->geo.ncell);
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_links(lbm_domain d, int64_t* cell, int32_t* dir, double* q,
+                                 uint8_t* fallback) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  const size_t n = d->geo.link_cell.size();
+  if (cell) std::memcpy(cell, d->geo.link_cell.data(), n * 8);
+  if (dir) std::memcpy(dir, d->geo.link_dir.data(), n * 4);
+  if (q) std::memcpy(q, d->geo.link_q.data(), n * 8);
+  if (fallback) std::memcpy(fallback, d->geo.link_fallback.data(), n);
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ binding
+
+LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* stream) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  if (!workspace) return fail(d, LBM_ERR_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(d, LBM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < d->total)
+    return fail(d, LBM_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(d->total) + " bytes");
+  d->bound = false;
+  d->ws = (char*)workspace;
+  d->ws_bytes = bytes;
+  d->stream = (hipStream_t)stream;
+  d->buf[0] = d->ws + d->off_buf[0];
+  d->buf[1] = d->ws + d->off_buf[1];
+  d->cur = 0;
+  d->flags = (uint32_t*)(d->ws + d->off_flags);
+  d->link_slot = (long long*)(d->ws + d->off_slot);
+  d->link_coef = (double*)(d->ws + d->off_coef);
+  d->partials = (double*)(d->ws + d->off_part);
+  d->result = (double*)(d->ws + d->off_res);
+  d->stage = (double*)(d->ws + d->off_stage);
+
+  const int64_t n = d->geo.ncell;
+  HIP_OK(d, hipMemcpyAsync(d->flags, d->geo.flags.data(), n * 4, hipMemcpyHostToDevice,
+                           d->stream));
+  // Wall-link coefficients into the slot of the solid pull source of each
+  // link: link (c, j) is pulled as direction k = opp(j) from c + e_j.
+  const size_t nl = d->geo.link_cell.size();
+  std::vector<long long> slot(nl);
+  std::vector<double> coef(nl);
+  const int nx = d->geo.nx, ny = d->geo.ny, nz = d->geo.nz;
+  for (size_t i = 0; i < nl; ++i) {
+    const int64_t c = d->geo.link_cell[i];
+    const int j = d->geo.link_dir[i];
+    const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+    const int xs = (x + kLat.ex[j] + nx) % nx, ys = (y + kLat.ey[j] + ny) % ny,
+              zs = (z + kLat.ez[j] + nz) % nz;
+    const int64_t s = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+    slot[i] = (long long)kLat.opp[j] * d->stride + s;
+    const double q = d->geo.link_q[i];
+    // eq. (CLI): a = (1 - 2q)/(1 + 2q); links without a second fluid node
+    // fall back to simple bounce-back (a = 0)
+    coef[i] = (d->p.wall == LBM_WALL_CLI && !d->geo.link_fallback[i])
+                  ? (1.0 - 2.0 * q) / (1.0 + 2.0 * q)
+                  : 0.0;
+  }
+  if (nl) {
+    HIP_OK(d, hipMemcpyAsync(d->link_slot, slot.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
+    HIP_OK(d, hipMemcpyAsync(d->link_coef, coef.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
+  }
+  const long long nel = (long long)kQ * d->stride;
+  if (d->p.storage == LBM_FP64) {
+    fill_kernel<double><<<2048, 256, 0, d->stream>>>((double*)d->buf[0], nel);
+    fill_kernel<double><<<2048, 256, 0, d->stream>>>((double*)d->buf[1], nel);
+    if (nl)
+      scatter_kernel<double><<<(int)std::min<size_t>((nl + 255) / 256, 65535), 256, 0, d->stream>>>(
+          (double*)d->buf[0], (double*)d->buf[1], d->link_slot, d->link_coef, (long long)nl);
+  } else {
+    fill_kernel<float><<<2048, 256, 0, d->stream>>>((float*)d->buf[0], nel);
+    fill_kernel<float><<<2048, 256, 0, d->stream>>>((float*)d->buf[1], nel);
+    if (nl)
+      scatter_kernel<float><<<(int)std::min<size_t>((nl + 255) / 256, 65535), 256, 0, d->stream>>>(
+          (float*)d->buf[0], (float*)d->buf[1], d->link_slot, d->link_coef, (long long)nl);
+  }
+  HIP_OK(d, hipGetLastError());
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  d->bound = true;
+  d->unstable = false;
+  return LBM_OK;  // buffers are zero: the rest state g = 0
+}
+
+// ------------------------------------------------------------------ state
+
+LBM_API lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const double* u0) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  const int64_t n = d->geo.ncell;
+  const size_t chunk = d->stage_cells;
+  std::vector<double> host(chunk * 4);
+  for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
+    const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+    for (int i = 0; i < m; ++i) {
+      host[i] = drho0 ? drho0[c0 + i] : 0.0;
+      host[m + i] = u0 ? u0[c0 + i] : 0.0;
+      host[2 * m + i] = u0 ? u0[n + c0 + i] : 0.0;
+      host[3 * m + i] = u0 ? u0[2 * n + c0 + i] : 0.0;
+    }
+    HIP_OK(d, hipMemcpyAsync(d->stage, host.data(), (size_t)m * 4 * 8, hipMemcpyHostToDevice,
+                             d->stream));
+    if (d->p.storage == LBM_FP64)
+      launch_init<double>(d, (int)c0, m);
+    else
+      launch_init<float>(d, (int)c0, m);
+    HIP_OK(d, hipGetLastError());
+    HIP_OK(d, hipStreamSynchronize(d->stream));
+  }
+  d->unstable = false;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!g) return fail(d, LBM_ERR_INVALID_ARG, "g is NULL");
+  const int64_t n = d->geo.ncell;
+  const size_t chunk = d->stage_cells * 4;
+  for (int k = 0; k < kQ; ++k) {
+    char* plane = (char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
+    for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
+      const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+      HIP_OK(d, hipMemcpyAsync(d->stage, g + (size_t)k * n + c0, (size_t)m * 8,
+                               hipMemcpyHostToDevice, d->stream));
+      if (d->p.storage == LBM_FP64)
+        set_plane_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>((double*)plane, d->flags,
+                                                                        (int)c0, m, d->stage);
+      else
+        set_plane_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>((float*)plane, d->flags,
+                                                                       (int)c0, m, d->stage);
+      HIP_OK(d, hipGetLastError());
+      HIP_OK(d, hipStreamSynchronize(d->stream));
+    }
+  }
+  d->unstable = false;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_state(lbm_domain d, double* g) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!g) return fail(d, LBM_ERR_INVALID_ARG, "g is NULL");
+  const int64_t n = d->geo.ncell;
+  const size_t chunk = d->stage_cells * 4;
+  for (int k = 0; k < kQ; ++k) {
+    const char* plane = (const char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
+    for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
+      const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+      if (d->p.storage == LBM_FP64)
+        get_plane_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>(
+            (const double*)plane, d->flags, (int)c0, m, d->stage);
+      else
+        get_plane_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>(
+            (const float*)plane, d->flags, (int)c0, m, d->stage);
+      HIP_OK(d, hipGetLastError());
+      HIP_OK(d, hipMemcpyAsync(g + (size_t)k * n + c0, d->stage, (size_t)m * 8,
+                               hipMemcpyDeviceToHost, d->stream));
+      HIP_OK(d, hipStreamSynchronize(d->stream));
+    }
+  }
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+
+LBM_API lbm_status lbm_step(lbm_domain d, int64_t n) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (n < 0) return fail(d, LBM_ERR_INVALID_ARG, "n must be >= 0");
+  if (d->unstable) return fail(d, LBM_ERR_STATE, "state is unstable; re-initialise first");
+  return enqueue_steps(d, n);
+}
+
+LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_steps,
+                                       int64_t* steps_done, double* residual) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (max_steps < 0 || !(tol >= 0)) return fail(d, LBM_ERR_INVALID_ARG, "bad tol or max_steps");
+  if (d->unstable) return fail(d, LBM_ERR_STATE, "state is unstable; re-initialise first");
+  const double cs2 = 1.0 / 3.0;
+  const double ncell = (double)d->geo.ncell;
+  double v[kRedVals];
+  st = reduce_state(d, v);
+  if (st != LBM_OK) return st;
+  double prev = v[0] / ncell, res = INFINITY;
+  int64_t done = 0;
+  int below = 0;
+  lbm_status out = LBM_ERR_NOT_CONVERGED;
+  while (done < max_steps) {
+    const int64_t m = std::min<int64_t>(d->p.check_interval, max_steps - done);
+    st = enqueue_steps(d, m);
+    if (st != LBM_OK) return st;
+    done += m;
+    st = reduce_state(d, v);
+    if (st != LBM_OK) return st;
+    const double U = v[0] / ncell;
+    if (v[5] > 0 || !std::isfinite(U) || v[4] > cs2) {
+      d->unstable = true;
+      out = LBM_ERR_UNSTABLE;
+      d->err = "non-finite state or |u| above the sound speed";
+      break;
+    }
+    res = U != 0.0 ? std::fabs(U - prev) / std::fabs(U) : (U == prev ? 0.0 : INFINITY);
+    prev = U;
+    below = res < tol ? below + 1 : 0;
+    if (below >= 3) {
+      out = LBM_OK;
+      break;
+    }
+  }
+  if (steps_done) *steps_done = done;
+  if (residual) *residual = res;
+  return out;
+}
+
+// --------------------------------------------------------------- observables
+
+LBM_API lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  const int64_t n = d->geo.ncell;
+  const size_t chunk = d->stage_cells;
+  std::vector<double> host(chunk * 4);
+  for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
+    const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+    if (d->p.storage == LBM_FP64)
+      macro_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>(
+          (const double*)d->buf[d->cur], d->flags, d->stride, (int)c0, m, d->stage);
+    else
+      macro_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>(
+          (const float*)d->buf[d->cur], d->flags, d->stride, (int)c0, m, d->stage);
+    HIP_OK(d, hipGetLastError());
+    HIP_OK(d, hipMemcpyAsync(host.data(), d->stage, (size_t)m * 4 * 8, hipMemcpyDeviceToHost,
+                             d->stream));
+    HIP_OK(d, hipStreamSynchronize(d->stream));
+    for (int i = 0; i < m; ++i) {
+      if (drho) drho[c0 + i] = host[i];
+      if (u) {
+        u[c0 + i] = host[m + i];
+        u[n + c0 + i] = host[2 * m + i];
+        u[2 * n + c0 + i] = host[3 * m + i];
+      }
+    }
+  }
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
+                                     double* total_drho) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  double v[kRedVals];
+  st = reduce_state(d, v);
+  if (st != LBM_OK) return st;
+  const double n = (double)d->geo.ncell;
+  if (U) {
+    U[0] = v[0] / n;
+    U[1] = v[1] / n;
+    U[2] = v[2] / n;
+  }
+  if (max_speed) *max_speed = v[5] > 0 ? NAN : std::sqrt(v[4]);
+  if (total_drho) *total_drho = v[3];
+  return LBM_OK;
+}
+
+// eq. (Darcy): K_D = mu U / |grad P| with mu = nu (rho0 = 1), |grad P| = dp/nx,
+// dp = delta_rho / 3.
+LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (d->p.delta_rho == 0.0) return fail(d, LBM_ERR_STATE, "delta_rho is zero");
+  double U[3];
+  st = lbm_mean_velocity(d, U, nullptr, nullptr);
+  if (st != LBM_OK) return st;
+  const double dp = d->p.delta_rho / 3.0;
+  if (K_D) *K_D = d->nu * U[0] * d->geo.nx / dp;
+  if (U_x) *U_x = U[0];
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!F) return fail(d, LBM_ERR_INVALID_ARG, "F is NULL");
+  const StepParams sp = step_params(d);
+  const bool cli = d->p.wall == LBM_WALL_CLI;
+  if (d->p.storage == LBM_FP64) {
+    if (cli)
+      drag_kernel<double, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const double*)d->buf[d->cur], d->flags, sp, d->partials);
+    else
+      drag_kernel<double, kSBB><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const double*)d->buf[d->cur], d->flags, sp, d->partials);
+  } else {
+    if (cli)
+      drag_kernel<float, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const float*)d->buf[d->cur], d->flags, sp, d->partials);
+    else
+      drag_kernel<float, kSBB><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const float*)d->buf[d->cur], d->flags, sp, d->partials);
+  }
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, -1, d->result);
+  HIP_OK(d, hipGetLastError());
+  double v[kRedVals];
+  HIP_OK(d, hipMemcpyAsync(v, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  F[0] = v[0];
+  F[1] = v[1];
+  F[2] = v[2];
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  if (!std::isfinite(delta_rho)) return fail(d, LBM_ERR_INVALID_ARG, "delta_rho must be finite");
+  d->p.delta_rho = delta_rho;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_synchronize(lbm_domain d) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_destroy(lbm_domain d) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  if (d->bound) (void)hipStreamSynchronize(d->stream);
+  delete d;
+  return LBM_OK;
+}
+
+LBM_API const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_WORKSPACE: return "workspace missing or too small";
+    case LBM_ERR_DEVICE: return "device error";
+    case LBM_ERR_UNSTABLE: return "unstable state";
+    case LBM_ERR_NOT_CONVERGED: return "not converged";
+    case LBM_ERR_STATE: return "invalid state for this call";
+  }
+  return "unknown status";
+}
+
+LBM_API const char* lbm_last_error(lbm_domain d) {
+  return d ? d->err.c_str() : g_create_error.c_str();
+}

@@ -1,0 +1,146 @@
+"""Host-side checks of liblbm.so that need no GPU: exported symbols, argument
+validation, and the host geometry against the oracle's own geometry."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1508_02960_amd import inputs, lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_header_function():
+    lib = lbm.library()
+    names = _header_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(lbm.EXPORTS)
+
+
+def _create(shape=(8, 9, 10), **kw):
+    nz, ny, nx = shape
+    p = lbm.Params(nx, ny, nz, kw.get("tau", 0.8), kw.get("magic", 3 / 16),
+                   kw.get("delta_rho", 0.0), kw.get("collision", 1), kw.get("wall", 0),
+                   kw.get("storage", 1), kw.get("check_interval", 100))
+    mask = kw.get("mask", np.zeros(shape, np.uint8))
+    h = C.c_void_p()
+    st = lbm.library().lbm_create_domain(
+        None if mask is None else mask.ctypes.data_as(C.c_void_p), kw.get("spheres"),
+        kw.get("n_spheres", 0), C.byref(p), C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(magic=0.0), dict(magic=0.8),
+    dict(collision=3), dict(wall=2), dict(storage=7), dict(check_interval=-1),
+    dict(delta_rho=float("inf")), dict(mask=None),
+])
+def test_invalid_arguments_are_rejected(kw):
+    st, h = _create(**kw)
+    assert st == 1 and not h.value
+    assert lbm.library().lbm_last_error(None)
+
+
+def test_invalid_dimensions_and_geometry():
+    lib = lbm.library()
+    for shape in [(0, 4, 4), (4, -1, 4)]:
+        nz, ny, nx = shape
+        p = lbm.Params(nx, ny, nz, 0.8, 0.1875, 0.0, 1, 0, 1, 0)
+        h = C.c_void_p()
+        assert lib.lbm_create_domain(None, None, 0, C.byref(p), C.byref(h)) == 1
+    # all solid: no fluid cell
+    st, h = _create(mask=np.ones((4, 4, 4), np.uint8), shape=(4, 4, 4))
+    assert st == 1 and b"fluid" in lib.lbm_last_error(None)
+    # both a mask and spheres
+    sp = (lbm.Sphere * 1)(lbm.Sphere(2, 2, 2, 1.0))
+    st, h = _create(mask=np.zeros((4, 4, 4), np.uint8), shape=(4, 4, 4), spheres=sp, n_spheres=1)
+    assert st == 1
+    # bad radius / centre
+    for s in [lbm.Sphere(2, 2, 2, 0.0), lbm.Sphere(2, 2, 2, 4.0), lbm.Sphere(5, 2, 2, 1.0)]:
+        sp = (lbm.Sphere * 1)(s)
+        st, h = _create(mask=None, shape=(4, 4, 4), spheres=sp, n_spheres=1)
+        assert st == 1
+
+
+def test_unbound_domain_rejects_device_calls():
+    st, h = _create()
+    assert st == 0
+    lib = lbm.library()
+    try:
+        assert lib.lbm_step(h, 1) == 6
+        U = np.zeros(3)
+        assert lib.lbm_mean_velocity(h, U.ctypes.data_as(C.c_void_p), None, None) == 6
+        ws = C.c_void_p(0)
+        assert lib.lbm_bind(h, ws, 0, None) == 2
+    finally:
+        lib.lbm_destroy(h)
+
+
+def test_info_and_workspace_size():
+    shape = (16, 12, 20)
+    d = lbm.Domain(shape, tau=0.8, spheres=inputs.centred_sphere(shape, 9.0), bind=False,
+                   wall="cli")
+    info = d.info
+    assert info.n_cells == 16 * 12 * 20
+    assert info.plane_stride >= info.n_cells
+    assert info.workspace_bytes >= 2 * 19 * info.plane_stride * 4 + 4 * info.n_cells
+    assert info.bytes_per_fluid_update == 152
+    assert abs(info.nu - 0.1) < 1e-15 and abs(info.omega_plus - 1.25) < 1e-15
+    d64 = lbm.Domain(shape, tau=0.8, spheres=inputs.centred_sphere(shape, 9.0), bind=False,
+                     storage="fp64")
+    assert d64.info.bytes_per_fluid_update == 304
+    d.close()
+    d64.close()
+
+
+GEOMETRIES = [
+    ("centred-32", (32, 32, 32), lambda s: inputs.centred_sphere(s, 24.0)),
+    ("random", (13, 17, 21), lambda s: inputs.random_spheres(s, 5, (1.5, 4.5), seed=7)),
+    ("random-dense", (12, 12, 12), lambda s: inputs.random_spheres(s, 9, (2.0, 3.5), seed=8)),
+    ("sc-array", (24, 24, 24), lambda s: inputs.simple_cubic_array(2, 12, 9.0)),
+]
+
+
+@pytest.mark.parametrize("name,shape,make", GEOMETRIES, ids=[g[0] for g in GEOMETRIES])
+def test_host_geometry_matches_oracle(orc, name, shape, make):
+    """Mask bit-exact, same link set, q within 1e-14, same fallback links."""
+    sp = make(shape)
+    d = lbm.Domain(shape, tau=0.8, spheres=sp, wall="cli", bind=False)
+    mask = d.mask()
+    omask = orc.voxelise(shape, sp)
+    assert np.array_equal(mask, omask)
+    assert d.n_fluid == int((omask == 0).sum())
+    cell, dirs, q, fb = d.links()
+    Q = orc.wall_q(omask, sp)
+    ncell = int(np.prod(shape))
+    oj, oc = np.nonzero(Q.reshape(19, ncell) >= 0)
+    order = np.lexsort((oj, oc))
+    assert np.array_equal(cell, oc[order]) and np.array_equal(dirs, oj[order])
+    assert np.max(np.abs(q - Q.reshape(19, ncell)[dirs, cell])) < 1e-14
+    e, _, _ = orc.lattice()
+    nz, ny, nx = shape
+    x, y, z = cell % nx, (cell // nx) % ny, cell // (nx * ny)
+    xb, yb, zb = (x - e[dirs, 0]) % nx, (y - e[dirs, 1]) % ny, (z - e[dirs, 2]) % nz
+    assert np.array_equal(fb, omask[zb, yb, xb])
+    assert d.info.n_fallback == int(fb.sum())
+    d.close()
+
+
+def test_mask_input_gives_half_distance():
+    shape = (6, 7, 8)
+    m = inputs.random_mask(shape, 0.3, seed=1)
+    d = lbm.Domain(shape, tau=0.9, mask=m, wall="cli", bind=False)
+    assert np.array_equal(d.mask(), m)
+    _, _, q, _ = d.links()
+    assert len(q) > 0 and np.all(q == 0.5)
+    d.close()

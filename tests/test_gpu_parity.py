@@ -1,0 +1,231 @@
+"""GPU library vs the FP64 oracle on identical seeded inputs (through the C ABI).
+
+Tolerances (norm-wise, max |a - b| / max |b| over fluid cells):
+  FP64 storage: 1e-12 on populations, velocity and permeability;
+  FP32 storage: 1e-5 on velocity.
+"""
+import numpy as np
+import pytest
+
+from paper_1508_02960_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+COMBOS = [(c, w) for c in ("srt", "trt", "mrt") for w in ("sbb", "cli")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.library()
+    yield
+    torch.cuda.synchronize()
+
+
+def rel(a, b, fluid=None):
+    if fluid is not None:
+        a = a[..., fluid]
+        b = b[..., fluid]
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def _pair(orc, shape, storage="fp64", **kw):
+    o = orc.Oracle(shape, **{k: v for k, v in kw.items() if k != "check_interval"})
+    d = lbm.Domain(shape, storage=storage, **kw)
+    return o, d
+
+
+@pytest.mark.parametrize("collision,wall", COMBOS)
+def test_fp64_step_parity_random_state(orc, collision, wall):
+    """Ragged box (nx = 70 is not a multiple of the 64-lane row, ny odd),
+    random spheres with fallback links, pressure jump, random state."""
+    shape = (11, 13, 70)
+    sp = inputs.random_spheres(shape, 6, (1.5, 4.0), seed=21)
+    o, d = _pair(orc, shape, tau=0.7, magic=0.21, delta_rho=3e-3, collision=collision,
+                 wall=wall, spheres=sp)
+    fluid = o.mask == 0
+    g0 = inputs.random_populations(shape, 1e-3, seed=22)
+    o.set_state(g0)
+    d.set_state(g0)
+    assert rel(d.get_state(), o.g, fluid) == 0.0
+    for n in (1, 4):
+        o.step(n)
+        d.step(n)
+        r = rel(d.get_state(), o.g, fluid)
+        assert r < 1e-12, (n, r)
+    d.close()
+
+
+@pytest.mark.parametrize("collision,wall", COMBOS)
+def test_fp32_velocity_parity(orc, collision, wall):
+    shape = (17, 24, 40)
+    sp = inputs.random_spheres(shape, 5, (2.0, 5.0), seed=31)
+    o, d = _pair(orc, shape, storage="fp32", tau=0.8, magic=3 / 16, delta_rho=1e-3,
+                 collision=collision, wall=wall, spheres=sp)
+    u0 = inputs.random_velocity(shape, 1e-2, seed=32)
+    o.init(u0=u0)
+    d.init_equilibrium(u0=u0)
+    o.step(20)
+    d.step(20)
+    fluid = o.mask == 0
+    _, uo = o.macroscopic()
+    _, ud = d.macroscopic()
+    assert rel(ud, uo, fluid) < 1e-5
+    d.close()
+
+
+def test_config1_fp64_full_run(orc):
+    """32^3 cell, centred sphere D = 24, TRT Lambda = 3/16, SBB, FP64,
+    delta_rho = 2.15e-6 (Re_p ~ 1e-3), rest start, 2000 steps."""
+    shape = (32, 32, 32)
+    kw = dict(tau=0.8, magic=3 / 16, delta_rho=2.15e-6, collision="trt", wall="sbb",
+              spheres=inputs.centred_sphere(shape, 24.0))
+    o, d = _pair(orc, shape, **kw)
+    o.init()
+    o.step(2000)
+    d.step(2000)
+    K, U = d.permeability()
+    Uo = o.mean_velocity()[0]
+    assert abs(U / Uo - 1) < 1e-12
+    assert abs(K / o.permeability() - 1) < 1e-12
+    assert 18.0 < K < 19.0
+    fluid = o.mask == 0
+    _, uo = o.macroscopic()
+    _, ud = d.macroscopic()
+    assert rel(ud, uo, fluid) < 1e-12
+    d.close()
+
+
+def test_bench_configuration_fp32(orc):
+    """The benchmarked workload: 128^3, centred sphere D = 100, TRT-CLI, FP32,
+    tau = 0.8, Lambda = 3/16; full-field velocity after 3 steps from a
+    perturbed equilibrium."""
+    shape = (128, 128, 128)
+    sp = inputs.centred_sphere(shape, 100.0)
+    o, d = _pair(orc, shape, storage="fp32", tau=0.8, magic=3 / 16, delta_rho=1e-4,
+                 collision="trt", wall="cli", spheres=sp)
+    u0 = inputs.random_velocity(shape, 1e-3, seed=41)
+    o.init(u0=u0)
+    d.init_equilibrium(u0=u0)
+    o.step(3)
+    d.step(3)
+    fluid = o.mask == 0
+    _, uo = o.macroscopic()
+    _, ud = d.macroscopic()
+    assert rel(ud, uo, fluid) < 1e-5
+    d.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_observables_parity(orc, storage, tol):
+    shape = (20, 18, 24)
+    sp = inputs.random_spheres(shape, 4, (2.0, 4.0), seed=51)
+    o, d = _pair(orc, shape, storage=storage, tau=0.9, magic=0.25, delta_rho=2e-3,
+                 collision="trt", wall="cli", spheres=sp)
+    u0 = inputs.random_velocity(shape, 5e-3, seed=52)
+    drho0 = inputs.random_velocity(shape, 1e-3, seed=53)[0]
+    o.init(drho0=drho0, u0=u0)
+    d.init_equilibrium(drho0=drho0, u0=u0)
+    o.step(7)
+    d.step(7)
+    fluid = o.mask == 0
+    ro, uo = o.macroscopic()
+    rd, ud = d.macroscopic()
+    assert rel(rd, ro, fluid) < tol * 10 and rel(ud, uo, fluid) < tol
+    U, vmax, tot = d.mean_velocity()
+    Uo = o.mean_velocity()
+    assert np.max(np.abs(U - Uo)) < tol * np.max(np.abs(Uo))
+    assert abs(vmax - np.sqrt((uo ** 2).sum(axis=0)).max()) < tol * vmax
+    K, Ux = d.permeability()
+    assert abs(K / o.permeability() - 1) < tol
+    F, Fo = d.drag(), o.drag()
+    assert np.max(np.abs(F - Fo)) < tol * 10 * np.max(np.abs(Fo))
+    d.close()
+
+
+def test_no_solid_exact_acceleration():
+    """Without solids U_x(n) = n drho / (3 nx) (pressure jump is the only force)."""
+    shape = (5, 6, 9)
+    d = lbm.Domain(shape, tau=0.7, delta_rho=1e-4, storage="fp64",
+                   mask=np.zeros(shape, np.uint8))
+    d.step(25)
+    U, _, tot = d.mean_velocity()
+    assert abs(U[0] - 25 * 1e-4 / 27) < 1e-16 and abs(tot) < 1e-15
+    d.close()
+
+
+def test_poiseuille_exact_on_gpu():
+    """Plane channel with TRT Lambda = 3/16 and SBB reaches the exact parabola
+    (walls half-way, Sec. 2.1); FP64, converged with run_to_residual."""
+    H, tau, nx = 10, 0.9, 4
+    shape = (2, H + 2, nx)
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, H + 1, :] = 1
+    d = lbm.Domain(shape, tau=tau, magic=3 / 16, delta_rho=1e-5, storage="fp64", mask=mask,
+                   check_interval=200)
+    status, steps, res = d.run_to_residual(1e-13, 200000)
+    assert status == "converged", (status, steps, res)
+    _, u = d.macroscopic()
+    G = 1e-5 / 3 / nx
+    nu = (tau - 0.5) / 3
+    y = np.arange(1, H + 1)
+    exact = G / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+    assert np.max(np.abs(u[0, 0, 1:H + 1, 0] - exact)) < 1e-10 * exact.max()
+    d.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 1, 5), (2, 3, 600), (4, 70, 3)])
+def test_edge_shapes_match_oracle(orc, shape):
+    """Degenerate boxes: one cell, a line, rows longer than one workgroup."""
+    rng = np.random.default_rng(61)
+    mask = (rng.uniform(size=shape) < 0.2).astype(np.uint8)
+    mask.flat[0] = 0
+    o, d = _pair(orc, shape, tau=0.75, magic=0.2, delta_rho=1e-3, collision="trt",
+                 wall="cli", mask=mask)
+    g0 = inputs.random_populations(shape, 1e-3, seed=62)
+    o.set_state(g0)
+    d.set_state(g0)
+    o.step(3)
+    d.step(3)
+    assert rel(d.get_state(), o.g, o.mask == 0) < 1e-12
+    d.close()
+
+
+def test_runs_are_bitwise_deterministic():
+    shape = (16, 16, 32)
+    sp = inputs.random_spheres(shape, 3, (2.0, 4.0), seed=71)
+    outs = []
+    for _ in range(2):
+        d = lbm.Domain(shape, tau=0.8, delta_rho=1e-3, wall="cli", spheres=sp)
+        d.step(50)
+        outs.append((d.get_state(), d.mean_velocity()[0]))
+        d.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_unstable_state_is_detected():
+    """tau near 1/2 with a huge pressure drop blows up; the run reports it and
+    the domain refuses further steps until re-initialised."""
+    shape = (8, 8, 8)
+    d = lbm.Domain(shape, tau=0.5001, magic=0.25, delta_rho=0.5, storage="fp32",
+                   spheres=inputs.centred_sphere(shape, 5.0), check_interval=50)
+    status, steps, _ = d.run_to_residual(1e-8, 20000)
+    assert status == "unstable"
+    with pytest.raises(lbm.LbmError):
+        d.step(1)
+    d.init_equilibrium()
+    d.step(1)
+    d.close()
+
+
+def test_not_converged_reports_steps():
+    shape = (8, 8, 8)
+    d = lbm.Domain(shape, tau=0.8, delta_rho=1e-5, spheres=inputs.centred_sphere(shape, 5.0),
+                   check_interval=10)
+    status, steps, res = d.run_to_residual(1e-14, 30)
+    assert status == "not_converged" and steps == 30 and res > 0
+    d.close()
