@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 TRT MLUPS + %HBM roofline; time-to-steady-state (plain vs warm-start)"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1508_02960_amd", "csrc", "kernels.hpp")
 
 WORKLOADS = {
@@ -49,7 +49,7 @@ def stored_traffic(workload: str, n_fluid: int):
     """HBM bytes per step-kernel launch from committed rocprofv3 counters, or
     None if they were taken on a different kernel source or workload."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(PROFILES, f"step_kernel_{workload}_traffic.json")) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None

@@ -152,6 +152,50 @@ __device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
   }
 }
 
+// ------------------------------------------------------------ reductions
+// FP64 sums over fluid cells: [0..2] sum u, [3] sum drho, [4] max |u|^2,
+// [5] count of non-finite cells.  Deterministic: fixed grid, fixed per-thread
+// order, fixed trees, no atomics.
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+constexpr int kRedVals = 8;
+constexpr int kMaxWaves = 8;  // blocks of up to 512 threads
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Block reduction of NV doubles (kind 0 = sum, 1 = max): wavefront shuffles,
+// then one LDS slot per wavefront folded in wavefront order.  Every thread of
+// the block must call it.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&kind)[NV], double* out) {
+  __shared__ double sh[kMaxWaves][NV];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int nwaves = (blockDim.x * blockDim.y + 63) >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = kind[i] ? wave_max(v[i]) : wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[wv][i] = v[i];
+  __syncthreads();
+  if (tid < NV) {
+    const int i = tid;
+    double a = sh[0][i];
+    for (int w = 1; w < nwaves; ++w) a = kind[i] ? fmax(a, sh[w][i]) : a + sh[w][i];
+    out[i] = a;
+  }
+}
+
 // ---------------------------------------------------------------- the step
 
 // Flat cell index of the node at (x + dx, y + dy, z + dz) given the wrapped
@@ -165,21 +209,15 @@ struct Nbr {
   }
 };
 
+// One time step for the node (x, y, z), fluid, with flag word fl: pull,
+// wall rule, pressure jump, collision, store.  Returns the pre-collision
+// moments (which the collision conserves) for the optional reduction.
 template <typename S, int COLL, int WALL>
-__global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
-                                                   S* __restrict__ dst,
-                                                   const uint32_t* __restrict__ flags,
-                                                   const StepParams p) {
+__device__ __forceinline__ void update_node(const S* __restrict__ src, S* __restrict__ dst,
+                                            const StepParams& p, int x, int y, int z, int c,
+                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[4]) {
   using C = typename ComputeOf<S>::type;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= p.nx || y >= p.ny) return;
   const int nx = p.nx, plane = p.nx * p.ny;
-  const int c = x + nx * y + plane * z;
-  const uint32_t fl = flags[c];
-  if (fl & kSolid) return;
-
   Nbr n;
   n.xs[0] = x == 0 ? nx - 1 : x - 1;
   n.xs[1] = x;
@@ -239,6 +277,7 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
     if (!(fl & (1u << 14))) g[14] -= jd;
   }
 
+  moments(g, mom[0], mom[1], mom[2], mom[3]);
   if constexpr (COLL == kSRT) {
     collide_srt<C>(g, (C)p.omega_p);
   } else if constexpr (COLL == kTRT) {
@@ -251,43 +290,67 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
   for (int k = 0; k < kQ; ++k) dst[k * st + c] = (S)g[k];
 }
 
-// ------------------------------------------------------------ reductions
-// FP64 sums over fluid cells of the stored state: [0..2] sum u, [3] sum drho,
-// [4] max |u|^2, [5] count of non-finite cells.  Deterministic: fixed grid,
-// fixed per-thread order, fixed tree.
-
-constexpr int kRedThreads = 256;
-constexpr int kRedBlocks = 1024;
-constexpr int kRedVals = 8;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  return v;
-}
-
-// Block reduction of kRedVals doubles; kinds: 0 = sum, 1 = max.
-template <int NV>
-__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&kind)[NV], double* out) {
-  __shared__ double sh[kRedThreads / 64][NV];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = kind[i] ? wave_max(v[i]) : wave_sum(v[i]);
-  if (lane == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sh[wv][i] = v[i];
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    const int i = threadIdx.x;
-    double a = sh[0][i];
-    for (int w = 1; w < kRedThreads / 64; ++w) a = kind[i] ? fmax(a, sh[w][i]) : a + sh[w][i];
-    out[i] = a;
+// The fused stream-and-collide step over the box.  Block (bx, by) covers
+// full x rows (bx >= nx, up to 512) so that the +-1 shifted row reads of a
+// row stay inside one workgroup.  With RED the block also writes FP64
+// partial sums of the state it produced (u, drho, max |u|^2, non-finite
+// count) to partials[block].
+template <typename S, int COLL, int WALL, bool RED>
+__global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
+                                                   S* __restrict__ dst,
+                                                   const uint32_t* __restrict__ flags,
+                                                   const StepParams p,
+                                                   double* __restrict__ partials) {
+  using C = typename ComputeOf<S>::type;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool inside = x < p.nx && y < p.ny;
+  const int c = x + p.nx * y + p.nx * p.ny * z;
+  if constexpr (!RED) {
+    if (!inside) return;
+    const uint32_t fl = flags[c];
+    if (fl & kSolid) return;
+    C mom[4];
+    update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
+  } else {
+    double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t fl = inside ? flags[c] : kSolid;
+    if (!(fl & kSolid)) {
+      C mom[4];
+      update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
+      const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
+      const double u2 = ux * ux + uy * uy + uz * uz;
+      v[0] = ux;
+      v[1] = uy;
+      v[2] = uz;
+      v[3] = rho;
+      if (isfinite(u2) && isfinite(rho))
+        v[4] = u2;
+      else
+        v[5] = 1.0;
+    }
+    const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
+    const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
   }
+}
+
+// Fold n partial vectors into gridDim.x vectors: block b takes a contiguous
+// chunk in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const double* __restrict__ in,
+                                                                      long long n, int max_slot,
+                                                                      double* __restrict__ out) {
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int kind[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (max_slot >= 0) kind[max_slot] = 1;
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long b0 = blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+  for (long long b = b0 + threadIdx.x; b < b1; b += kRedThreads)
+#pragma unroll
+    for (int i = 0; i < kRedVals; ++i)
+      v[i] = kind[i] ? fmax(v[i], in[b * kRedVals + i]) : v[i] + in[b * kRedVals + i];
+  block_reduce<kRedVals>(v, kind, out + (long long)blockIdx.x * kRedVals);
 }
 
 template <typename S>

@@ -37,13 +37,18 @@ struct lbm_domain_s {
   uint32_t* flags = nullptr;
   long long* link_slot = nullptr;
   double* link_coef = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;   // per-block partial sums
+  double* partials2 = nullptr;  // second-stage partial sums
+  long long n_partials = 0;     // capacity of partials (vectors)
   double* result = nullptr;
+  // replayable launch sequences: kGraphSteps steps starting from buffer p
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   double* stage = nullptr;
   size_t stage_cells = 0;  // cells per staging chunk (4 doubles each)
   // layout offsets
   size_t off_buf[2] = {0, 0}, off_flags = 0, off_slot = 0, off_coef = 0, off_part = 0,
-         off_res = 0, off_stage = 0, total = 0;
+         off_part2 = 0, off_res = 0, off_stage = 0, total = 0;
 };
 
 namespace {
@@ -68,6 +73,17 @@ lbm_status fail(lbm_domain d, lbm_status s, const std::string& msg) {
 // HBM channel: round the cell count up to 1024 elements, plus 512 elements.
 long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
 
+// Workgroups cover full x rows (up to 512 cells) and 256/bx rows in y.
+dim3 step_block(int nx) {
+  const int bx = std::min(512, ((nx + 63) / 64) * 64);
+  const int by = std::max(1, 256 / bx);
+  return dim3(bx, by, 1);
+}
+dim3 step_grid(int nx, int ny, int nz) {
+  const dim3 b = step_block(nx);
+  return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y, nz);
+}
+
 void layout(lbm_domain d) {
   const int64_t n = d->geo.ncell;
   d->stride = plane_stride(n);
@@ -85,8 +101,12 @@ void layout(lbm_domain d) {
   o += align256(std::max<size_t>(nl, 1) * 8);
   d->off_coef = o;
   o += align256(std::max<size_t>(nl, 1) * 8);
+  const dim3 sg = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
+  d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
   d->off_part = o;
-  o += align256((size_t)kRedBlocks * kRedVals * 8);
+  o += align256((size_t)d->n_partials * kRedVals * 8);
+  d->off_part2 = o;
+  o += align256((size_t)kRedThreads * kRedVals * 8);
   d->off_res = o;
   o += align256(kRedVals * 8);
   // staging: at least one z-plane of cells, at least 1M cells, 4 doubles each
@@ -97,23 +117,24 @@ void layout(lbm_domain d) {
   d->total = o;
 }
 
-template <typename S>
-void launch_step_t(lbm_domain d, const void* src, void* dst, const StepParams& sp) {
-  const int bx = std::min(512, ((d->geo.nx + 63) / 64) * 64);
-  const int by = std::max(1, 256 / bx);
-  dim3 block(bx, by, 1);
-  dim3 grid((d->geo.nx + bx - 1) / bx, (d->geo.ny + by - 1) / by, d->geo.nz);
-  const S* s = (const S*)src;
-  S* t = (S*)dst;
-  const int key = d->p.collision * 2 + d->p.wall;
-  switch (key) {
-    case 0: step_kernel<S, kSRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
-    case 1: step_kernel<S, kSRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
-    case 2: step_kernel<S, kTRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
-    case 3: step_kernel<S, kTRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
-    case 4: step_kernel<S, kMRT, kSBB><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
-    default: step_kernel<S, kMRT, kCLI><<<grid, block, 0, d->stream>>>(s, t, d->flags, sp); break;
+template <typename S, bool RED>
+const void* step_fn(int collision, int wall) {
+  switch (collision * 2 + wall) {
+    case 0: return (const void*)step_kernel<S, kSRT, kSBB, RED>;
+    case 1: return (const void*)step_kernel<S, kSRT, kCLI, RED>;
+    case 2: return (const void*)step_kernel<S, kTRT, kSBB, RED>;
+    case 3: return (const void*)step_kernel<S, kTRT, kCLI, RED>;
+    case 4: return (const void*)step_kernel<S, kMRT, kSBB, RED>;
+    default: return (const void*)step_kernel<S, kMRT, kCLI, RED>;
   }
+}
+
+const void* step_function(lbm_domain d, bool red) {
+  if (d->p.storage == LBM_FP64)
+    return red ? step_fn<double, true>(d->p.collision, d->p.wall)
+               : step_fn<double, false>(d->p.collision, d->p.wall);
+  return red ? step_fn<float, true>(d->p.collision, d->p.wall)
+             : step_fn<float, false>(d->p.collision, d->p.wall);
 }
 
 StepParams step_params(lbm_domain d) {
@@ -131,18 +152,102 @@ StepParams step_params(lbm_domain d) {
   return sp;
 }
 
+// Steps replayed as one graph launch (an even count keeps the buffer parity).
+constexpr int kGraphSteps = 32;
+
+void drop_graphs(lbm_domain d) {
+  for (int i = 0; i < 2; ++i) {
+    if (d->graph_exec[i]) (void)hipGraphExecDestroy(d->graph_exec[i]);
+    if (d->graph[i]) (void)hipGraphDestroy(d->graph[i]);
+    d->graph_exec[i] = nullptr;
+    d->graph[i] = nullptr;
+  }
+}
+
+// One step launch from buffer d->cur; red adds the block partial sums.
+lbm_status launch_step(lbm_domain d, bool red) {
+  StepParams sp = step_params(d);
+  const void* src = d->buf[d->cur];
+  void* dst = d->buf[1 - d->cur];
+  uint32_t* fl = d->flags;
+  double* part = d->partials;
+  void* args[] = {(void*)&src, (void*)&dst, (void*)&fl, (void*)&sp, (void*)&part};
+  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz), block = step_block(d->geo.nx);
+  HIP_OK(d, hipLaunchKernel(step_function(d, red), grid, block, args, 0, d->stream));
+  d->cur = 1 - d->cur;
+  return LBM_OK;
+}
+
+// Build the graph of kGraphSteps plain steps starting from buffer `from`:
+// kernel nodes only, each depending on the previous one.
+lbm_status build_graph(lbm_domain d, int from) {
+  hipGraph_t g = nullptr;
+  HIP_OK(d, hipGraphCreate(&g, 0));
+  StepParams sp = step_params(d);
+  uint32_t* fl = d->flags;
+  double* part = d->partials;
+  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz), block = step_block(d->geo.nx);
+  const void* fn = step_function(d, false);
+  hipGraphNode_t prev = nullptr;
+  for (int i = 0; i < kGraphSteps; ++i) {
+    const void* src = d->buf[(from + i) & 1];
+    void* dst = d->buf[(from + i + 1) & 1];
+    void* args[] = {(void*)&src, (void*)&dst, (void*)&fl, (void*)&sp, (void*)&part};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(d, LBM_ERR_DEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+    }
+    prev = node;
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(d, LBM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  d->graph[from] = g;
+  d->graph_exec[from] = ex;
+  return LBM_OK;
+}
+
 lbm_status enqueue_steps(lbm_domain d, int64_t n) {
-  const StepParams sp = step_params(d);
+  while (n >= kGraphSteps) {
+    if (!d->graph_exec[d->cur]) {
+      lbm_status st = build_graph(d, d->cur);
+      if (st != LBM_OK) return st;
+    }
+    HIP_OK(d, hipGraphLaunch(d->graph_exec[d->cur], d->stream));
+    n -= kGraphSteps;  // even count: d->cur unchanged
+  }
   for (int64_t i = 0; i < n; ++i) {
-    const void* src = d->buf[d->cur];
-    void* dst = d->buf[1 - d->cur];
-    if (d->p.storage == LBM_FP64)
-      launch_step_t<double>(d, src, dst, sp);
-    else
-      launch_step_t<float>(d, src, dst, sp);
-    d->cur = 1 - d->cur;
+    lbm_status st = launch_step(d, false);
+    if (st != LBM_OK) return st;
   }
   HIP_OK(d, hipGetLastError());
+  return LBM_OK;
+}
+
+// One step with the fused FP64 reduction; vals (host) after a stream sync.
+lbm_status step_and_reduce(lbm_domain d, double* vals) {
+  lbm_status st = launch_step(d, true);
+  if (st != LBM_OK) return st;
+  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
+  const long long nb = (long long)grid.x * grid.y * grid.z;
+  reduce_partials_kernel<<<kRedThreads, kRedThreads, 0, d->stream>>>(d->partials, nb, 4,
+                                                                     d->partials2);
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials2, kRedThreads, 4, d->result);
+  HIP_OK(d, hipGetLastError());
+  HIP_OK(d, hipMemcpyAsync(vals, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));
   return LBM_OK;
 }
 
@@ -297,6 +402,8 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->link_slot = (long long*)(d->ws + d->off_slot);
   d->link_coef = (double*)(d->ws + d->off_coef);
   d->partials = (double*)(d->ws + d->off_part);
+  d->partials2 = (double*)(d->ws + d->off_part2);
+  drop_graphs(d);
   d->result = (double*)(d->ws + d->off_res);
   d->stage = (double*)(d->ws + d->off_stage);
 
@@ -456,11 +563,11 @@ LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_ste
   lbm_status out = LBM_ERR_NOT_CONVERGED;
   while (done < max_steps) {
     const int64_t m = std::min<int64_t>(d->p.check_interval, max_steps - done);
-    st = enqueue_steps(d, m);
+    st = enqueue_steps(d, m - 1);
+    if (st != LBM_OK) return st;
+    st = step_and_reduce(d, v);  // the m-th step also reduces the new state
     if (st != LBM_OK) return st;
     done += m;
-    st = reduce_state(d, v);
-    if (st != LBM_OK) return st;
     const double U = v[0] / ncell;
     if (v[5] > 0 || !std::isfinite(U) || v[4] > cs2) {
       d->unstable = true;
@@ -582,6 +689,7 @@ LBM_API lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho) {
   if (!d) return LBM_ERR_INVALID_ARG;
   if (!std::isfinite(delta_rho)) return fail(d, LBM_ERR_INVALID_ARG, "delta_rho must be finite");
   d->p.delta_rho = delta_rho;
+  drop_graphs(d);
   return LBM_OK;
 }
 
@@ -595,6 +703,7 @@ LBM_API lbm_status lbm_synchronize(lbm_domain d) {
 LBM_API lbm_status lbm_destroy(lbm_domain d) {
   if (!d) return LBM_ERR_INVALID_ARG;
   if (d->bound) (void)hipStreamSynchronize(d->stream);
+  drop_graphs(d);
   delete d;
   return LBM_OK;
 }

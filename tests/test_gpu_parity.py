@@ -229,3 +229,59 @@ def test_not_converged_reports_steps():
     status, steps, res = d.run_to_residual(1e-14, 30)
     assert status == "not_converged" and steps == 30 and res > 0
     d.close()
+
+
+def test_graph_replay_matches_single_launches():
+    """lbm_step(n >= 32) replays a graph of step launches; it must give the
+    same bits as n separate one-step calls, from either buffer parity."""
+    shape = (12, 10, 20)
+    sp = inputs.random_spheres(shape, 3, (2.0, 3.5), seed=81)
+    a = lbm.Domain(shape, tau=0.8, delta_rho=1e-3, wall="cli", spheres=sp)
+    b = lbm.Domain(shape, tau=0.8, delta_rho=1e-3, wall="cli", spheres=sp)
+    u0 = inputs.random_velocity(shape, 1e-2, seed=82)
+    a.init_equilibrium(u0=u0)
+    b.init_equilibrium(u0=u0)
+    a.step(1)
+    a.step(70)
+    for _ in range(71):
+        b.step(1)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
+def test_pressure_drop_change_rebuilds_graph(orc):
+    shape = (10, 9, 14)
+    sp = inputs.random_spheres(shape, 2, (2.0, 3.0), seed=83)
+    o = orc.Oracle(shape, tau=0.9, magic=3 / 16, delta_rho=1e-3, wall="cli", spheres=sp)
+    d = lbm.Domain(shape, tau=0.9, magic=3 / 16, delta_rho=1e-3, wall="cli", spheres=sp,
+                   storage="fp64")
+    o.init()
+    o.step(64)
+    d.step(64)
+    o.p.drho = -2e-3
+    d.set_delta_rho(-2e-3)
+    o.step(64)
+    d.step(64)
+    fluid = o.mask == 0
+    assert rel(d.get_state(), o.g, fluid) < 1e-12
+    d.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_run_to_residual_matches_oracle(orc, storage, tol):
+    """The checks use the reduction fused into the step kernel; the stopping
+    step and the converged permeability agree with the oracle's loop."""
+    shape = (12, 12, 12)
+    kw = dict(tau=1.0, magic=3 / 16, delta_rho=1e-5, collision="trt", wall="cli",
+              spheres=inputs.centred_sphere(shape, 7.0))
+    o = orc.Oracle(shape, **kw)
+    d = lbm.Domain(shape, storage=storage, check_interval=50, **kw)
+    o.init()
+    so, no, ro = o.run_to_residual(1e-7, 20000, interval=50)
+    sd, nd, rd = d.run_to_residual(1e-7, 20000)
+    assert so == sd == "converged"
+    assert abs(nd - no) <= (0 if storage == "fp64" else 100)
+    K, _ = d.permeability()
+    assert abs(K / o.permeability() - 1) < max(tol, 1e-6)
+    d.close()
