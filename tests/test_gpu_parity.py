@@ -285,3 +285,31 @@ def test_run_to_residual_matches_oracle(orc, storage, tol):
     K, _ = d.permeability()
     assert abs(K / o.permeability() - 1) < max(tol, 1e-6)
     d.close()
+
+
+def test_forchheimer_sweep_matches_oracle(orc):
+    """Three pressure drops (Re_p 0.01 .. 5) on a 16^3 cell, each run to a
+    1e-10 residual on GPU (FP64) and in the oracle; the per-run permeability
+    and the fitted K_D and beta agree."""
+    from paper_1508_02960_amd import observables as ob
+    from paper_1508_02960_amd.sweep import run_sweep
+
+    shape, D, tau = (16, 16, 16), 10.0, 0.8
+    res = run_sweep(shape, D, tau=tau, storage="fp64", re_targets=[0.01, 1.0, 5.0],
+                    K_guess=20.0, tol=1e-10, scale_start=False, check_interval=100)
+    g, U = [], []
+    for r in res["runs"]:
+        assert r["status"] == "converged"
+        o = orc.Oracle(shape, tau=tau, magic=3 / 16, delta_rho=r["delta_rho"], wall="cli",
+                       spheres=inputs.centred_sphere(shape, D))
+        o.init()
+        st, _, _ = o.run_to_residual(1e-10, 400000, interval=100)
+        assert st == "converged"
+        Uo = o.mean_velocity()[0]
+        assert abs(r["U"] / Uo - 1) < 1e-7
+        g.append(ob.pressure_gradient(r["delta_rho"], shape[2]))
+        U.append(Uo)
+    K, beta, _ = ob.forchheimer_fit(g, U, tau)
+    assert abs(res["K_D"] / K - 1) < 1e-7
+    assert abs(res["beta"] / beta - 1) < 1e-5
+    assert res["beta"] > 0
