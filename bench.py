@@ -36,8 +36,23 @@ WORKLOADS = {
     "sc128_d100_trt_cli_fp32": ((128, 128, 128), 100.0, "trt", "cli", "fp32", 0.8, 3 / 16, 1.5e-4),
     "sc256_d200_trt_cli_fp32": ((256, 256, 256), 200.0, "trt", "cli", "fp32", 0.8, 3 / 16, 1.5e-4),
     "sc32_d24_trt_sbb_fp64": ((32, 32, 32), 24.0, "trt", "sbb", "fp64", 0.8, 3 / 16, 2.15e-6),
+    "sc128_d100_trt_cli_fp16": ((128, 128, 128), 100.0, "trt", "cli", "fp16", 0.8, 3 / 16, 1.5e-4),
+    "sc128_d100_trt_cli_bf16": ((128, 128, 128), 100.0, "trt", "cli", "bf16", 0.8, 3 / 16, 1.5e-4),
+    "sc128_d100_mrt_cli_fp32": ((128, 128, 128), 100.0, "mrt", "cli", "fp32", 0.8, 3 / 16, 1.5e-4),
+    "sc512_d240x8_trt_cli_fp32": ((512, 512, 512), 240.0, "trt", "cli", "fp32", 0.5005, 6e-6, 1e-5),
+    "sc512_d240x8_trt_cli_fp16": ((512, 512, 512), 240.0, "trt", "cli", "fp16", 0.5005, 6e-6, 1e-5),
 }
 DEFAULT_WORKLOAD = "sc128_d100_trt_cli_fp32"
+
+
+def workload_spheres(shape, dia):
+    """One centred sphere per 256^3 cell (2 x 2 x 2 cells at 512^3)."""
+    from paper_1508_02960_amd import inputs
+
+    n = shape[0]
+    if n > 256:
+        return inputs.simple_cubic_array(n // 256, 256, dia)
+    return inputs.centred_sphere(shape, dia)
 
 
 def kernel_source_hash() -> str:
@@ -68,7 +83,7 @@ def cpu_baseline(wl, budget_s: float):
     from paper_1508_02960_amd import inputs
 
     o = oracle.Oracle(shape, tau=tau, magic=magic, delta_rho=drho, collision=coll, wall=wall,
-                      spheres=inputs.centred_sphere(shape, dia))
+                      spheres=workload_spheres(shape, dia))
     o.init()
     n_fluid = int((o.mask == 0).sum())
     t0 = time.perf_counter()
@@ -115,7 +130,7 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d = lbm.Domain(shape, tau=tau, magic=magic, delta_rho=drho, collision=coll, wall=wall,
-                   storage=storage, spheres=inputs.centred_sphere(shape, dia), device=dev,
+                   storage=storage, spheres=workload_spheres(shape, dia), device=dev,
                    check_interval=100)
     n_fluid, n_cells = d.n_fluid, d.ncell
     stream = d.stream
@@ -172,7 +187,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if storage == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16 storage, f32 compute",
+                  "bf16": "bf16 storage, f32 compute"}[storage],
         "data": "synthetic",
         "config": {
             "workload": args.workload,

@@ -59,8 +59,30 @@ typedef enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 } lbm_collision;
 typedef enum { LBM_WALL_SBB = 0, LBM_WALL_CLI = 1 } lbm_wall;
 
 /* Storage precision of the populations (deviations g = f - w).  FP64 computes
- * in double, FP32 in float. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1 } lbm_storage;
+ * in double; the others compute in float.  FP16 and BF16 store
+ * h_k = sigma g_k / w_k in 16 bits with stochastic rounding (each stored
+ * value is the 16-bit neighbour below or above with probability given by the
+ * distance, from a counter-based hash of cell, direction and step, so runs
+ * stay reproducible); the _RNE variants round to nearest even, which biases
+ * slowly varying (Stokes) fields by percents.  Dividing by the
+ * weight puts all directions on one scale, and sigma (a power of two, see
+ * lbm_info.storage_scale) keeps FP16 values in its normal range.  sigma is
+ * chosen when a state is set and, for FP16, moved by exact power-of-two
+ * rescaling at the residual checks of lbm_run_to_residual when the largest
+ * stored magnitude leaves [2^6, 2^13] (it is set to map the largest
+ * magnitude of the state and of delta_rho to 2^10).  Between checks the
+ * magnitude may grow 64x before FP16 overflows; lbm_step alone does not
+ * rescale.  BF16 keeps sigma = 1.  Reductions are FP64 in every mode.
+ * Stochastic-rounding modes launch every step separately (no graph replay),
+ * since each step needs its own seed. */
+typedef enum {
+  LBM_FP64 = 0,
+  LBM_FP32 = 1,
+  LBM_FP16 = 2,     /* stochastic rounding */
+  LBM_BF16 = 3,     /* stochastic rounding */
+  LBM_FP16_RNE = 4, /* round to nearest even */
+  LBM_BF16_RNE = 5  /* round to nearest even */
+} lbm_storage;
 
 /* A sphere in lattice units; spheres and their periodic images may overlap.
  * Radii must be positive and smaller than the smallest box edge. */
@@ -90,6 +112,7 @@ typedef struct {
   double omega_plus;       /* 1/tau                                             */
   double omega_minus;      /* TRT antisymmetric rate from Lambda                */
   int64_t bytes_per_fluid_update; /* algorithmic HBM bytes per fluid-cell update */
+  double storage_scale;    /* sigma of 16-bit storage (1 otherwise)             */
 } lbm_info;
 
 /* Create a domain on the host (no device work).  Sec. 3 / Sec. 2.2.1.

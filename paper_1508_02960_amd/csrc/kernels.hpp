@@ -34,16 +34,156 @@ struct StepParams {
   double omega_m;     // TRT antisymmetric rate
   double s_e;         // MRT energy modes 1, 2
   double s_zeta;      // MRT remaining kinetic modes
+  double sigma;       // 16-bit storage: stored h_k = sigma * g_k / w_k
+  unsigned seed;      // stochastic rounding: per-step seed
+};
+
+// ------------------------------------------------------------ storage types
+// FP64 and FP32 store g_k directly.  The 16-bit types store h_k = sigma g_k /
+// w_k: dividing by the weight puts the 19 directions on one scale and sigma
+// (a power of two) moves that scale into the normal range of the format.
+// Values are computed in FP32 and rounded to nearest-even on store.
+
+struct bf16_t {
+  uint16_t u;
+};
+using fp16_t = _Float16;
+
+template <typename S>
+struct Storage {
+  using compute = float;
+  static constexpr bool scaled = false;
+  __device__ __host__ static float to_float(S v) { return (float)v; }
+  __device__ __host__ static S from_float(float v) { return (S)v; }
+};
+template <>
+struct Storage<double> {
+  using compute = double;
+  static constexpr bool scaled = false;
+  __device__ __host__ static double to_float(double v) { return v; }
+  __device__ __host__ static double from_float(double v) { return v; }
+};
+template <>
+struct Storage<fp16_t> {
+  using compute = float;
+  static constexpr bool scaled = true;
+  __device__ __host__ static float to_float(fp16_t v) { return (float)v; }
+  __device__ __host__ static fp16_t from_float(float v) { return (fp16_t)v; }
+};
+template <>
+struct Storage<bf16_t> {
+  using compute = float;
+  static constexpr bool scaled = true;
+  __device__ __host__ static float to_float(bf16_t v) {
+    return __builtin_bit_cast(float, (uint32_t)v.u << 16);
+  }
+  // round to nearest, ties to even; NaN stays a quiet NaN
+  __device__ __host__ static bf16_t from_float(float f) {
+    uint32_t b = __builtin_bit_cast(uint32_t, f);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return bf16_t{(uint16_t)((b >> 16) | 0x40u)};
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return bf16_t{(uint16_t)(b >> 16)};
+  }
+};
+
+// Stochastic-rounding variants: the stored value is the 16-bit neighbour
+// below or above (in magnitude) with probabilities given by the distance, so
+// the rounding error has zero mean.  r is a uniform 32-bit random word.
+struct fp16s_t {
+  _Float16 v;
+};
+struct bf16s_t {
+  uint16_t u;
+};
+template <>
+struct Storage<fp16s_t> {
+  using compute = float;
+  static constexpr bool scaled = true;
+  static constexpr bool stochastic = true;
+  __device__ __host__ static float to_float(fp16s_t v) { return (float)v.v; }
+  __device__ __host__ static fp16s_t from_float(float v) { return fp16s_t{(_Float16)v}; }
+  // Integer form: below the FP16 spacing of |f| lie `drop` bits of the FP32
+  // pattern (13 in the normal range, more below 2^-14); adding a uniform
+  // random number of that width to the magnitude and clearing those bits
+  // gives the lower or upper neighbour with the right probabilities (a carry
+  // into the exponent is the next power of two).  Magnitudes below 2^-24,
+  // far under the scaled range, round to nearest.
+  __device__ static fp16s_t from_float_sr(float f, uint32_t r) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, f);
+    const uint32_t mag = b & 0x7FFFFFFFu;
+    const int e = (int)(mag >> 23) - 127;
+    if (mag >= 0x477FE000u || e < -24) return fp16s_t{(_Float16)f};  // >= 65504, inf, NaN, tiny
+    const int drop = e < -14 ? -1 - e : 13;
+    const uint32_t mask = (1u << drop) - 1u;
+    const uint32_t q = (mag + (r >> (32 - drop))) & ~mask;
+    return fp16s_t{(_Float16)__builtin_bit_cast(float, q | (b & 0x80000000u))};
+  }
+};
+template <>
+struct Storage<bf16s_t> {
+  using compute = float;
+  static constexpr bool scaled = true;
+  static constexpr bool stochastic = true;
+  __device__ __host__ static float to_float(bf16s_t v) {
+    return __builtin_bit_cast(float, (uint32_t)v.u << 16);
+  }
+  __device__ __host__ static bf16s_t from_float(float f) {
+    return bf16s_t{Storage<bf16_t>::from_float(f).u};
+  }
+  // BF16 is the top half of FP32 (sign-magnitude): adding a random 16-bit
+  // word to the magnitude bits and truncating rounds the magnitude
+  // stochastically.
+  __device__ static bf16s_t from_float_sr(float f, uint32_t r) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, f);
+    if ((b & 0x7F800000u) == 0x7F800000u) return from_float(f);
+    return bf16s_t{(uint16_t)((b + (r >> 16)) >> 16)};
+  }
 };
 
 template <typename S>
-struct ComputeOf {
-  using type = float;
+struct IsStochastic {
+  static constexpr bool value = false;
 };
 template <>
-struct ComputeOf<double> {
-  using type = double;
+struct IsStochastic<fp16s_t> {
+  static constexpr bool value = true;
 };
+template <>
+struct IsStochastic<bf16s_t> {
+  static constexpr bool value = true;
+};
+
+// Counter-based random word for (cell, direction, step seed): a 32-bit
+// integer finaliser (xor-shift / multiply rounds).
+__device__ __host__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+template <typename S>
+struct ComputeOf {
+  using type = typename Storage<S>::compute;
+};
+
+// Factor that turns a stored value of direction k into g_k (1 unless scaled).
+template <typename S, int K>
+__device__ __forceinline__ typename ComputeOf<S>::type decode_factor(double inv_sigma) {
+  using C = typename ComputeOf<S>::type;
+  if constexpr (Storage<S>::scaled) return (C)(kLat.w[K] * inv_sigma);
+  else return (C)1;
+}
+template <typename S, int K>
+__device__ __forceinline__ typename ComputeOf<S>::type encode_factor(double sigma) {
+  using C = typename ComputeOf<S>::type;
+  if constexpr (Storage<S>::scaled) return (C)(sigma / kLat.w[K]);
+  else return (C)1;
+}
+// Runtime-k versions for the set-up kernels.
+__device__ __host__ inline double weight_of(int k) { return k == 0 ? 1.0 / 3.0 : (k < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 // ---------------------------------------------------------------- collision
 // Input: post-streaming deviations g[19]; output overwrites g.
@@ -152,6 +292,18 @@ __device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
   }
 }
 
+// Set-up and reduction kernels convert one stored value at a runtime k.
+template <typename S>
+__device__ __forceinline__ double stored_to_g(S v, int k, double sigma) {
+  const double f = (double)Storage<S>::to_float(v);
+  return Storage<S>::scaled ? f * (weight_of(k) / sigma) : f;
+}
+template <typename S>
+__device__ __forceinline__ S g_to_stored(double g, int k, double sigma) {
+  using C = typename Storage<S>::compute;
+  return Storage<S>::from_float((C)(Storage<S>::scaled ? g * (sigma / weight_of(k)) : g));
+}
+
 // ------------------------------------------------------------ reductions
 // FP64 sums over fluid cells: [0..2] sum u, [3] sum drho, [4] max |u|^2,
 // [5] count of non-finite cells.  Deterministic: fixed grid, fixed per-thread
@@ -209,14 +361,19 @@ struct Nbr {
   }
 };
 
+// Weight class of direction k: 0 rest, 1 axis, 2 diagonal.
+__device__ __host__ constexpr int wclass(int k) { return k == 0 ? 0 : (k < 7 ? 1 : 2); }
+
 // One time step for the node (x, y, z), fluid, with flag word fl: pull,
 // wall rule, pressure jump, collision, store.  Returns the pre-collision
-// moments (which the collision conserves) for the optional reduction.
+// moments (which the collision conserves) and max_k |g*_k| / w_k of the
+// stored result, for the optional reduction.
 template <typename S, int COLL, int WALL>
 __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __restrict__ dst,
                                             const StepParams& p, int x, int y, int z, int c,
-                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[4]) {
+                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
+  using St = Storage<S>;
   const int nx = p.nx, plane = p.nx * p.ny;
   Nbr n;
   n.xs[0] = x == 0 ? nx - 1 : x - 1;
@@ -229,26 +386,36 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
   n.zs[1] = z * plane;
   n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
 
+  // stored -> g factors per weight class (1 for unscaled storage)
+  C dec[3] = {(C)1, (C)1, (C)1};
+  if constexpr (St::scaled) {
+    const double is = 1.0 / p.sigma;
+    dec[0] = (C)(kLat.w[0] * is);
+    dec[1] = (C)(kLat.w[1] * is);
+    dec[2] = (C)(kLat.w[7] * is);
+  }
+
   const long long st = p.stride;
   C g[kQ];
-  // pull: direction k arrives from x - e_k
+  // pull: direction k arrives from x - e_k (raw stored values)
 #pragma unroll
   for (int k = 0; k < kQ; ++k)
-    g[k] = (C)src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])];
+    g[k] = (C)St::to_float(src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])]);
 
-  // wall links: the pulled value is the stored coefficient a
+  // wall links: the pulled raw value is the stored coefficient a
   if (fl & kLinkMask) {
 #pragma unroll
     for (int k = 1; k < kQ; ++k) {
       if (fl & (1u << k)) {
         const int j = kLat.opp[k];
-        const C own_j = (C)src[j * st + c];
+        const C own_j = (C)St::to_float(src[j * st + c]) * dec[wclass(j)];
         if constexpr (WALL == kCLI) {
           const C a = g[k];
-          const C own_k = (C)src[k * st + c];
+          const C own_k = (C)St::to_float(src[k * st + c]) * dec[wclass(k)];
           // second node x_f2 = x + e_k (away from the wall), read across the
           // x-periodic plane with the pressure jump
-          C far_j = (C)src[j * st + n.at(kLat.ex[k], kLat.ey[k], kLat.ez[k])];
+          C far_j = (C)St::to_float(src[j * st + n.at(kLat.ex[k], kLat.ey[k], kLat.ez[k])]) *
+                    dec[wclass(j)];
           if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
           if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
           g[k] = a * far_j - a * own_k + own_j;
@@ -257,6 +424,12 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
         }
       }
     }
+  }
+  if constexpr (St::scaled) {
+    g[0] *= dec[0];
+#pragma unroll
+    for (int k = 1; k < kQ; ++k)
+      if (!(fl & (1u << k))) g[k] *= dec[wclass(k)];
   }
 
   // periodic pressure drop on pulls across the x-plane (not on wall links)
@@ -286,8 +459,28 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
     collide_mrt<C>(g, (C)p.omega_p, (C)p.s_e, (C)p.s_zeta);
   }
 
+  C enc[3] = {(C)1, (C)1, (C)1};
+  if constexpr (St::scaled) {
+    enc[0] = (C)(p.sigma / kLat.w[0]);
+    enc[1] = (C)(p.sigma / kLat.w[1]);
+    enc[2] = (C)(p.sigma / kLat.w[7]);
+  }
+  if constexpr (IsStochastic<S>::value) {
+    // one finalised hash per cell and step; direction k takes the high bits
+    // of (base + k * golden) * odd constant (multiplicative hashing)
+    const uint32_t base = hash32((uint32_t)c * 19u + p.seed);
 #pragma unroll
-  for (int k = 0; k < kQ; ++k) dst[k * st + c] = (S)g[k];
+    for (int k = 0; k < kQ; ++k)
+      dst[k * st + c] = St::from_float_sr(g[k] * enc[wclass(k)],
+                                          (base + (uint32_t)k * 0x9e3779b9u) * 0x85ebca6bu);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) dst[k * st + c] = St::from_float(g[k] * enc[wclass(k)]);
+  }
+  C m = (C)0;
+#pragma unroll
+  for (int k = 0; k < kQ; ++k) m = fmax(m, fabs(g[k]) * (C)(1.0 / kLat.w[k]));
+  mom[4] = m;
 }
 
 // The fused stream-and-collide step over the box.  Block (bx, by) covers
@@ -311,13 +504,13 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
     if (!inside) return;
     const uint32_t fl = flags[c];
     if (fl & kSolid) return;
-    C mom[4];
+    C mom[5];
     update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t fl = inside ? flags[c] : kSolid;
     if (!(fl & kSolid)) {
-      C mom[4];
+      C mom[5];
       update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
@@ -329,8 +522,9 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
         v[4] = u2;
       else
         v[5] = 1.0;
+      v[6] = isfinite((double)mom[4]) ? (double)mom[4] : 0.0;
     }
-    const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
+    const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
     const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
     block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
   }
@@ -339,11 +533,12 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
 // Fold n partial vectors into gridDim.x vectors: block b takes a contiguous
 // chunk in a fixed order.
 __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const double* __restrict__ in,
-                                                                      long long n, int max_slot,
+                                                                      long long n, int max_mask,
                                                                       double* __restrict__ out) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int kind[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (max_slot >= 0) kind[max_slot] = 1;
+  int kind[kRedVals];
+#pragma unroll
+  for (int i = 0; i < kRedVals; ++i) kind[i] = (max_mask >> i) & 1;
   const long long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long long b0 = blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
   for (long long b = b0 + threadIdx.x; b < b1; b += kRedThreads)
@@ -357,6 +552,7 @@ template <typename S>
 __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __restrict__ src,
                                                                    const uint32_t* __restrict__ flags,
                                                                    long long stride, int ncell,
+                                                                   double sigma,
                                                                    double* __restrict__ partials) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (long long c = blockIdx.x * kRedThreads + threadIdx.x; c < ncell;
@@ -364,7 +560,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __re
     if (flags[c] & kSolid) continue;
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = (double)src[k * stride + c];
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(src[k * stride + c], k, sigma);
     double rho, ux, uy, uz;
     moments<double>(g, rho, ux, uy, uz);
     const double u2 = ux * ux + uy * uy + uz * uz;
@@ -401,20 +597,20 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
     for (int k = 1; k < kQ; ++k) {
       if (!(fl & (1u << k))) continue;
       const int j = kLat.opp[k];
-      const double own_j = (double)src[j * st + c];
+      const double own_j = stored_to_g<S>(src[j * st + c], j, p.sigma);
       double back = own_j;
       if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double a = (double)src[k * st + sx + p.nx * (sy + p.ny * sz)];
+        const double a = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
         const int tx = x + kLat.ex[k];
         const int fx = (tx + p.nx) % p.nx, fy = (y + kLat.ey[k] + p.ny) % p.ny,
                   fz = (z + kLat.ez[k] + p.nz) % p.nz;
-        double far_j = (double)src[j * st + fx + p.nx * (fy + p.ny * fz)];
+        double far_j = stored_to_g<S>(src[j * st + fx + p.nx * (fy + p.ny * fz)], j, p.sigma);
         const double jw = kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag;
         if (tx >= p.nx) far_j -= jw;
         if (tx < 0) far_j += jw;
-        back = a * far_j - a * (double)src[k * st + c] + own_j;
+        back = a * far_j - a * stored_to_g<S>(src[k * st + c], k, p.sigma) + own_j;
       }
       const double tot = (own_j + kLat.w[j]) + (back + kLat.w[k]);
       v[0] += kLat.ex[j] * tot;
@@ -428,11 +624,12 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
 
 // Second pass: one block folds the per-block partials in a fixed order.
 __global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(const double* __restrict__ partials,
-                                                                   int nblocks, int max_slot,
+                                                                   int nblocks, int max_mask,
                                                                    double* __restrict__ out) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int kind[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (max_slot >= 0) kind[max_slot] = 1;
+  int kind[kRedVals];
+#pragma unroll
+  for (int i = 0; i < kRedVals; ++i) kind[i] = (max_mask >> i) & 1;
   for (int b = threadIdx.x; b < nblocks; b += kRedThreads)
 #pragma unroll
     for (int i = 0; i < kRedVals; ++i)
@@ -446,42 +643,47 @@ template <typename S>
 __global__ void fill_kernel(S* __restrict__ buf, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    buf[i] = (S)0;
+    buf[i] = Storage<S>::from_float(0);
 }
 
+// Wall-link coefficients (not scaled) into the solid-source slots of both buffers.
 template <typename S>
 __global__ void scatter_kernel(S* __restrict__ a, S* __restrict__ b,
                                const long long* __restrict__ slot,
                                const double* __restrict__ value, long long n) {
+  using C = typename Storage<S>::compute;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    a[slot[i]] = (S)value[i];
-    b[slot[i]] = (S)value[i];
+    const S v = Storage<S>::from_float((C)value[i]);
+    a[slot[i]] = v;
+    b[slot[i]] = v;
   }
 }
 
-// One direction plane, cells [c0, c0 + n), to/from a double staging buffer.
+// One direction plane k, cells [c0, c0 + n), to/from a double staging buffer
+// (values are g_k; 16-bit storage is decoded / encoded with sigma).
 template <typename S>
 __global__ void get_plane_kernel(const S* __restrict__ plane, const uint32_t* __restrict__ flags,
-                                 int c0, int n, double* __restrict__ out) {
+                                 int k, double sigma, int c0, int n, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = (flags[c0 + i] & kSolid) ? 0.0 : (double)plane[c0 + i];
+  out[i] = (flags[c0 + i] & kSolid) ? 0.0 : stored_to_g<S>(plane[c0 + i], k, sigma);
 }
 
 template <typename S>
-__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags, int c0,
-                                 int n, const double* __restrict__ in) {
+__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags, int k,
+                                 double sigma, int c0, int n, const double* __restrict__ in) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (!(flags[c0 + i] & kSolid)) plane[c0 + i] = (S)in[i];
+  if (!(flags[c0 + i] & kSolid)) plane[c0 + i] = g_to_stored<S>(in[i], k, sigma);
 }
 
 // g = g^eq(drho, u) for fluid cells [c0, c0 + n); stage = drho | ux | uy | uz
 // blocks of n doubles (all-zero staging gives the rest state).
 template <typename S>
 __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                               long long stride, int c0, int n, const double* __restrict__ stage) {
+                               long long stride, double sigma, int c0, int n,
+                               const double* __restrict__ stage) {
   using C = typename ComputeOf<S>::type;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -497,13 +699,14 @@ __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__
   LBM_EQ(17) LBM_EQ(18)
 #undef LBM_EQ
 #pragma unroll
-  for (int k = 0; k < kQ; ++k) buf[k * stride + c] = (S)g[k];
+  for (int k = 0; k < kQ; ++k) buf[k * stride + c] = g_to_stored<S>((double)g[k], k, sigma);
 }
 
 // drho, u of cells [c0, c0 + n) into stage (drho | ux | uy | uz blocks).
 template <typename S>
 __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                             long long stride, int c0, int n, double* __restrict__ stage) {
+                             long long stride, double sigma, int c0, int n,
+                             double* __restrict__ stage) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c = c0 + i;
@@ -511,13 +714,29 @@ __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restri
   if (!(flags[c] & kSolid)) {
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = (double)buf[k * stride + c];
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(buf[k * stride + c], k, sigma);
     moments<double>(g, rho, ux, uy, uz);
   }
   stage[i] = rho;
   stage[n + i] = ux;
   stage[2 * n + i] = uy;
   stage[3 * n + i] = uz;
+}
+
+// Multiply the stored values of fluid cells by a power of two (exact unless
+// a value leaves the normal range); used to move the 16-bit storage scale.
+template <typename S>
+__global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
+                               long long stride, int ncell, float factor) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    if (flags[c] & kSolid) continue;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      S* q = buf + k * stride + c;
+      *q = Storage<S>::from_float(Storage<S>::to_float(*q) * factor);
+    }
+  }
 }
 
 }  // namespace lbm

@@ -26,6 +26,8 @@ struct lbm_domain_s {
   long long stride = 0;  // elements per direction plane
   size_t elem = 0;       // bytes per stored population
   double nu = 0, omega_p = 0, omega_m = 0, s_e = 0, s_zeta = 0;
+  double sigma = 1.0;    // 16-bit storage scale (h = sigma g / w), a power of two
+  uint64_t step_count = 0;  // steps launched (seeds stochastic rounding)
   // device (inside the caller's workspace)
   bool bound = false;
   bool unstable = false;
@@ -41,11 +43,11 @@ struct lbm_domain_s {
   double* partials2 = nullptr;  // second-stage partial sums
   long long n_partials = 0;     // capacity of partials (vectors)
   double* result = nullptr;
+  double* stage = nullptr;
+  size_t stage_cells = 0;  // cells per staging chunk (4 doubles each)
   // replayable launch sequences: kGraphSteps steps starting from buffer p
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-  double* stage = nullptr;
-  size_t stage_cells = 0;  // cells per staging chunk (4 doubles each)
   // layout offsets
   size_t off_buf[2] = {0, 0}, off_flags = 0, off_slot = 0, off_coef = 0, off_part = 0,
          off_part2 = 0, off_res = 0, off_stage = 0, total = 0;
@@ -69,6 +71,36 @@ lbm_status fail(lbm_domain d, lbm_status s, const std::string& msg) {
       return fail((d), LBM_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Call f with a value of the storage type of the domain.
+template <class F>
+decltype(auto) with_storage(int storage, F&& f) {
+  switch (storage) {
+    case LBM_FP64: return f(double{});
+    case LBM_FP32: return f(float{});
+    case LBM_FP16: return f(fp16s_t{});
+    case LBM_BF16: return f(bf16s_t{});
+    case LBM_FP16_RNE: return f(fp16_t{});
+    default: return f(bf16_t{});
+  }
+}
+
+size_t storage_bytes(int storage) {
+  return storage == LBM_FP64 ? 8 : (storage == LBM_FP32 ? 4 : 2);
+}
+bool is_fp16(int storage) { return storage == LBM_FP16 || storage == LBM_FP16_RNE; }
+bool is_stochastic(int storage) { return storage == LBM_FP16 || storage == LBM_BF16; }
+
+// 16-bit storage keeps max_k |g_k| / w_k * sigma inside [kScaleLow, kScaleHigh]
+// (FP16 holds up to 65504, a growth of 64x from kScaleTarget between two
+// checks; its relative precision is the same from 2^-14 up).
+constexpr double kScaleTarget = 1024.0, kScaleHigh = 8192.0, kScaleLow = 64.0;
+
+// Power-of-two sigma that maps magnitude m to about kScaleTarget.
+double pick_sigma(double m) {
+  if (!(m > 0.0) || !std::isfinite(m)) return kScaleTarget;
+  return std::ldexp(1.0, (int)std::floor(std::log2(kScaleTarget / m)));
+}
+
 // Direction planes are padded so that the 19 streams do not start on the same
 // HBM channel: round the cell count up to 1024 elements, plus 512 elements.
 long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
@@ -87,7 +119,7 @@ dim3 step_grid(int nx, int ny, int nz) {
 void layout(lbm_domain d) {
   const int64_t n = d->geo.ncell;
   d->stride = plane_stride(n);
-  d->elem = d->p.storage == LBM_FP64 ? 8 : 4;
+  d->elem = storage_bytes(d->p.storage);
   size_t o = 0;
   const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
   d->off_buf[0] = o;
@@ -117,6 +149,23 @@ void layout(lbm_domain d) {
   d->total = o;
 }
 
+StepParams step_params(lbm_domain d) {
+  StepParams sp;
+  sp.nx = d->geo.nx;
+  sp.ny = d->geo.ny;
+  sp.nz = d->geo.nz;
+  sp.stride = d->stride;
+  sp.jump_axis = (1.0 / 18.0) * d->p.delta_rho;
+  sp.jump_diag = (1.0 / 36.0) * d->p.delta_rho;
+  sp.omega_p = d->omega_p;
+  sp.omega_m = d->omega_m;
+  sp.s_e = d->s_e;
+  sp.s_zeta = d->s_zeta;
+  sp.sigma = d->sigma;
+  sp.seed = hash32((uint32_t)d->step_count ^ hash32((uint32_t)(d->step_count >> 32) + 0x5bd1e995u));
+  return sp;
+}
+
 template <typename S, bool RED>
 const void* step_fn(int collision, int wall) {
   switch (collision * 2 + wall) {
@@ -130,26 +179,11 @@ const void* step_fn(int collision, int wall) {
 }
 
 const void* step_function(lbm_domain d, bool red) {
-  if (d->p.storage == LBM_FP64)
-    return red ? step_fn<double, true>(d->p.collision, d->p.wall)
-               : step_fn<double, false>(d->p.collision, d->p.wall);
-  return red ? step_fn<float, true>(d->p.collision, d->p.wall)
-             : step_fn<float, false>(d->p.collision, d->p.wall);
-}
-
-StepParams step_params(lbm_domain d) {
-  StepParams sp;
-  sp.nx = d->geo.nx;
-  sp.ny = d->geo.ny;
-  sp.nz = d->geo.nz;
-  sp.stride = d->stride;
-  sp.jump_axis = (1.0 / 18.0) * d->p.delta_rho;
-  sp.jump_diag = (1.0 / 36.0) * d->p.delta_rho;
-  sp.omega_p = d->omega_p;
-  sp.omega_m = d->omega_m;
-  sp.s_e = d->s_e;
-  sp.s_zeta = d->s_zeta;
-  return sp;
+  return with_storage(d->p.storage, [&](auto tag) -> const void* {
+    using S = decltype(tag);
+    return red ? step_fn<S, true>(d->p.collision, d->p.wall)
+               : step_fn<S, false>(d->p.collision, d->p.wall);
+  });
 }
 
 // Steps replayed as one graph launch (an even count keeps the buffer parity).
@@ -175,6 +209,7 @@ lbm_status launch_step(lbm_domain d, bool red) {
   const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz), block = step_block(d->geo.nx);
   HIP_OK(d, hipLaunchKernel(step_function(d, red), grid, block, args, 0, d->stream));
   d->cur = 1 - d->cur;
+  ++d->step_count;
   return LBM_OK;
 }
 
@@ -220,7 +255,8 @@ lbm_status build_graph(lbm_domain d, int from) {
 }
 
 lbm_status enqueue_steps(lbm_domain d, int64_t n) {
-  while (n >= kGraphSteps) {
+  // stochastic rounding needs a fresh seed per step: plain launches only
+  while (n >= kGraphSteps && !is_stochastic(d->p.storage)) {
     if (!d->graph_exec[d->cur]) {
       lbm_status st = build_graph(d, d->cur);
       if (st != LBM_OK) return st;
@@ -236,34 +272,62 @@ lbm_status enqueue_steps(lbm_domain d, int64_t n) {
   return LBM_OK;
 }
 
-// One step with the fused FP64 reduction; vals (host) after a stream sync.
-lbm_status step_and_reduce(lbm_domain d, double* vals) {
-  lbm_status st = launch_step(d, true);
-  if (st != LBM_OK) return st;
-  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
-  const long long nb = (long long)grid.x * grid.y * grid.z;
-  reduce_partials_kernel<<<kRedThreads, kRedThreads, 0, d->stream>>>(d->partials, nb, 4,
-                                                                     d->partials2);
-  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials2, kRedThreads, 4, d->result);
+lbm_status fetch_result(lbm_domain d, double* vals) {
   HIP_OK(d, hipGetLastError());
   HIP_OK(d, hipMemcpyAsync(vals, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
   HIP_OK(d, hipStreamSynchronize(d->stream));
   return LBM_OK;
 }
 
-// Reduce the current state; vals (host, kRedVals doubles) after a stream sync.
+// One step with the fused FP64 reduction; vals (host) after a stream sync:
+// [0..2] sum u, [3] sum drho, [4] max |u|^2, [5] non-finite cells,
+// [6] max_k |g_k| / w_k.
+lbm_status step_and_reduce(lbm_domain d, double* vals) {
+  lbm_status st = launch_step(d, true);
+  if (st != LBM_OK) return st;
+  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
+  const long long nb = (long long)grid.x * grid.y * grid.z;
+  const int mask = (1 << 4) | (1 << 6);
+  reduce_partials_kernel<<<kRedThreads, kRedThreads, 0, d->stream>>>(d->partials, nb, mask,
+                                                                     d->partials2);
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials2, kRedThreads, mask,
+                                                       d->result);
+  return fetch_result(d, vals);
+}
+
+// Reduce the stored current state; vals as above without slot 6.
 lbm_status reduce_state(lbm_domain d, double* vals) {
   const int ncell = (int)d->geo.ncell;
-  if (d->p.storage == LBM_FP64)
-    reduce_state_kernel<double><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-        (const double*)d->buf[d->cur], d->flags, d->stride, ncell, d->partials);
-  else
-    reduce_state_kernel<float><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-        (const float*)d->buf[d->cur], d->flags, d->stride, ncell, d->partials);
-  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 4, d->result);
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    reduce_state_kernel<S><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+        (const S*)d->buf[d->cur], d->flags, d->stride, ncell, d->sigma, d->partials);
+    return 0;
+  });
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 1 << 4,
+                                                       d->result);
+  return fetch_result(d, vals);
+}
+
+// Move the 16-bit storage scale so that the largest stored magnitude
+// (m * sigma) lies in [kScaleLow, kScaleHigh]; exact power-of-two rescaling
+// of the current buffer.  No-op for FP32/FP64 and for BF16 (whose exponent
+// range is that of FP32).
+lbm_status adjust_scale(lbm_domain d, double m) {
+  if (!is_fp16(d->p.storage) || !(m > 0.0) || !std::isfinite(m)) return LBM_OK;
+  const double stored = m * d->sigma;
+  if (stored >= kScaleLow && stored <= kScaleHigh) return LBM_OK;
+  const double ns = pick_sigma(m);
+  const float factor = (float)(ns / d->sigma);
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    rescale_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[d->cur], d->flags, d->stride,
+                                                   (int)d->geo.ncell, factor);
+    return 0;
+  });
   HIP_OK(d, hipGetLastError());
-  HIP_OK(d, hipMemcpyAsync(vals, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
-  HIP_OK(d, hipStreamSynchronize(d->stream));
+  d->sigma = ns;
+  drop_graphs(d);
   return LBM_OK;
 }
 
@@ -273,11 +337,22 @@ lbm_status check_ready(lbm_domain d) {
   return LBM_OK;
 }
 
-template <typename S>
-void launch_init(lbm_domain d, int c0, int n) {
-  const int bs = 256;
-  init_eq_kernel<S><<<(n + bs - 1) / bs, bs, 0, d->stream>>>((S*)d->buf[d->cur], d->flags,
-                                                                d->stride, c0, n, d->stage);
+// Largest |g_k| / w_k of an equilibrium with the given drho and u: the
+// equilibrium deviation over w is drho + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u.
+double eq_magnitude(double drho, double ux, double uy, double uz) {
+  const double a = std::fabs(ux) + std::fabs(uy) + std::fabs(uz);
+  const double u2 = ux * ux + uy * uy + uz * uz;
+  return std::fabs(drho) + 3.0 * a + 4.5 * a * a + 1.5 * u2;
+}
+
+// Scale for a new state of magnitude m (the pressure jump adds w delta_rho).
+void choose_sigma(lbm_domain d, double m) {
+  if (is_fp16(d->p.storage)) {
+    d->sigma = pick_sigma(std::max(m, std::fabs(d->p.delta_rho)));
+  } else {
+    d->sigma = 1.0;
+  }
+  drop_graphs(d);
 }
 
 }  // namespace
@@ -303,7 +378,7 @@ LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere
   if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return bad("tau must be finite and > 1/2");
   if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
   if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_CLI) return bad("unknown wall rule");
-  if (p.storage < LBM_FP64 || p.storage > LBM_FP32) return bad("unknown storage");
+  if (p.storage < LBM_FP64 || p.storage > LBM_BF16_RNE) return bad("unknown storage");
   if (p.collision == LBM_TRT && !(p.magic > 0.0 && p.magic <= 0.75))
     return bad("TRT magic parameter must lie in (0, 3/4]");
   if (!std::isfinite(p.delta_rho)) return bad("delta_rho must be finite");
@@ -345,6 +420,7 @@ LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere
   d->s_e = 1.0 / (0.5 + (p.tau - 0.5) / 4.6);
   d->s_zeta = 8.0 * (2.0 - d->omega_p) / (8.0 - d->omega_p);
   layout(d);
+  choose_sigma(d, 0.0);
   *out = d;
   return LBM_OK;
 }
@@ -361,6 +437,7 @@ LBM_API lbm_status lbm_get_info(lbm_domain d, lbm_info* info) {
   info->omega_plus = d->omega_p;
   info->omega_minus = d->omega_m;
   info->bytes_per_fluid_update = (int64_t)(2 * kQ * d->elem);
+  info->storage_scale = d->sigma;
   return LBM_OK;
 }
 
@@ -392,6 +469,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     return fail(d, LBM_ERR_WORKSPACE,
                 "workspace too small: need " + std::to_string(d->total) + " bytes");
   d->bound = false;
+  drop_graphs(d);
   d->ws = (char*)workspace;
   d->ws_bytes = bytes;
   d->stream = (hipStream_t)stream;
@@ -403,7 +481,6 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->link_coef = (double*)(d->ws + d->off_coef);
   d->partials = (double*)(d->ws + d->off_part);
   d->partials2 = (double*)(d->ws + d->off_part2);
-  drop_graphs(d);
   d->result = (double*)(d->ws + d->off_res);
   d->stage = (double*)(d->ws + d->off_stage);
 
@@ -436,21 +513,18 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     HIP_OK(d, hipMemcpyAsync(d->link_coef, coef.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
   }
   const long long nel = (long long)kQ * d->stride;
-  if (d->p.storage == LBM_FP64) {
-    fill_kernel<double><<<2048, 256, 0, d->stream>>>((double*)d->buf[0], nel);
-    fill_kernel<double><<<2048, 256, 0, d->stream>>>((double*)d->buf[1], nel);
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    fill_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[0], nel);
+    fill_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[1], nel);
     if (nl)
-      scatter_kernel<double><<<(int)std::min<size_t>((nl + 255) / 256, 65535), 256, 0, d->stream>>>(
-          (double*)d->buf[0], (double*)d->buf[1], d->link_slot, d->link_coef, (long long)nl);
-  } else {
-    fill_kernel<float><<<2048, 256, 0, d->stream>>>((float*)d->buf[0], nel);
-    fill_kernel<float><<<2048, 256, 0, d->stream>>>((float*)d->buf[1], nel);
-    if (nl)
-      scatter_kernel<float><<<(int)std::min<size_t>((nl + 255) / 256, 65535), 256, 0, d->stream>>>(
-          (float*)d->buf[0], (float*)d->buf[1], d->link_slot, d->link_coef, (long long)nl);
-  }
+      scatter_kernel<S><<<(int)std::min<size_t>((nl + 255) / 256, 65535), 256, 0, d->stream>>>(
+          (S*)d->buf[0], (S*)d->buf[1], d->link_slot, d->link_coef, (long long)nl);
+    return 0;
+  });
   HIP_OK(d, hipGetLastError());
   HIP_OK(d, hipStreamSynchronize(d->stream));
+  choose_sigma(d, 0.0);
   d->bound = true;
   d->unstable = false;
   return LBM_OK;  // buffers are zero: the rest state g = 0
@@ -462,22 +536,32 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const
   lbm_status st = check_ready(d);
   if (st != LBM_OK) return st;
   const int64_t n = d->geo.ncell;
+  double m = 0.0;
+  for (int64_t c = 0; c < n; ++c) {
+    if (d->geo.mask[c]) continue;
+    const double r = drho0 ? drho0[c] : 0.0;
+    const double ux = u0 ? u0[c] : 0.0, uy = u0 ? u0[n + c] : 0.0, uz = u0 ? u0[2 * n + c] : 0.0;
+    m = std::max(m, eq_magnitude(r, ux, uy, uz));
+  }
+  choose_sigma(d, m);
   const size_t chunk = d->stage_cells;
   std::vector<double> host(chunk * 4);
   for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
-    const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
-    for (int i = 0; i < m; ++i) {
+    const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+    for (int i = 0; i < cnt; ++i) {
       host[i] = drho0 ? drho0[c0 + i] : 0.0;
-      host[m + i] = u0 ? u0[c0 + i] : 0.0;
-      host[2 * m + i] = u0 ? u0[n + c0 + i] : 0.0;
-      host[3 * m + i] = u0 ? u0[2 * n + c0 + i] : 0.0;
+      host[cnt + i] = u0 ? u0[c0 + i] : 0.0;
+      host[2 * cnt + i] = u0 ? u0[n + c0 + i] : 0.0;
+      host[3 * cnt + i] = u0 ? u0[2 * n + c0 + i] : 0.0;
     }
-    HIP_OK(d, hipMemcpyAsync(d->stage, host.data(), (size_t)m * 4 * 8, hipMemcpyHostToDevice,
+    HIP_OK(d, hipMemcpyAsync(d->stage, host.data(), (size_t)cnt * 4 * 8, hipMemcpyHostToDevice,
                              d->stream));
-    if (d->p.storage == LBM_FP64)
-      launch_init<double>(d, (int)c0, m);
-    else
-      launch_init<float>(d, (int)c0, m);
+    with_storage(d->p.storage, [&](auto tag) {
+      using S = decltype(tag);
+      init_eq_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
+          (S*)d->buf[d->cur], d->flags, d->stride, d->sigma, (int)c0, cnt, d->stage);
+      return 0;
+    });
     HIP_OK(d, hipGetLastError());
     HIP_OK(d, hipStreamSynchronize(d->stream));
   }
@@ -490,19 +574,24 @@ LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
   if (st != LBM_OK) return st;
   if (!g) return fail(d, LBM_ERR_INVALID_ARG, "g is NULL");
   const int64_t n = d->geo.ncell;
+  double m = 0.0;
+  for (int k = 0; k < kQ; ++k)
+    for (int64_t c = 0; c < n; ++c)
+      if (!d->geo.mask[c]) m = std::max(m, std::fabs(g[(size_t)k * n + c]) / weight_of(k));
+  choose_sigma(d, m);
   const size_t chunk = d->stage_cells * 4;
   for (int k = 0; k < kQ; ++k) {
     char* plane = (char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
     for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
-      const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
-      HIP_OK(d, hipMemcpyAsync(d->stage, g + (size_t)k * n + c0, (size_t)m * 8,
+      const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+      HIP_OK(d, hipMemcpyAsync(d->stage, g + (size_t)k * n + c0, (size_t)cnt * 8,
                                hipMemcpyHostToDevice, d->stream));
-      if (d->p.storage == LBM_FP64)
-        set_plane_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>((double*)plane, d->flags,
-                                                                        (int)c0, m, d->stage);
-      else
-        set_plane_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>((float*)plane, d->flags,
-                                                                       (int)c0, m, d->stage);
+      with_storage(d->p.storage, [&](auto tag) {
+        using S = decltype(tag);
+        set_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
+            (S*)plane, d->flags, k, d->sigma, (int)c0, cnt, d->stage);
+        return 0;
+      });
       HIP_OK(d, hipGetLastError());
       HIP_OK(d, hipStreamSynchronize(d->stream));
     }
@@ -520,15 +609,15 @@ LBM_API lbm_status lbm_get_state(lbm_domain d, double* g) {
   for (int k = 0; k < kQ; ++k) {
     const char* plane = (const char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
     for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
-      const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
-      if (d->p.storage == LBM_FP64)
-        get_plane_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>(
-            (const double*)plane, d->flags, (int)c0, m, d->stage);
-      else
-        get_plane_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>(
-            (const float*)plane, d->flags, (int)c0, m, d->stage);
+      const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+      with_storage(d->p.storage, [&](auto tag) {
+        using S = decltype(tag);
+        get_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
+            (const S*)plane, d->flags, k, d->sigma, (int)c0, cnt, d->stage);
+        return 0;
+      });
       HIP_OK(d, hipGetLastError());
-      HIP_OK(d, hipMemcpyAsync(g + (size_t)k * n + c0, d->stage, (size_t)m * 8,
+      HIP_OK(d, hipMemcpyAsync(g + (size_t)k * n + c0, d->stage, (size_t)cnt * 8,
                                hipMemcpyDeviceToHost, d->stream));
       HIP_OK(d, hipStreamSynchronize(d->stream));
     }
@@ -575,6 +664,8 @@ LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_ste
       d->err = "non-finite state or |u| above the sound speed";
       break;
     }
+    st = adjust_scale(d, v[6]);
+    if (st != LBM_OK) return st;
     res = U != 0.0 ? std::fabs(U - prev) / std::fabs(U) : (U == prev ? 0.0 : INFINITY);
     prev = U;
     below = res < tol ? below + 1 : 0;
@@ -597,23 +688,23 @@ LBM_API lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u) {
   const size_t chunk = d->stage_cells;
   std::vector<double> host(chunk * 4);
   for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
-    const int m = (int)std::min<int64_t>((int64_t)chunk, n - c0);
-    if (d->p.storage == LBM_FP64)
-      macro_kernel<double><<<(m + 255) / 256, 256, 0, d->stream>>>(
-          (const double*)d->buf[d->cur], d->flags, d->stride, (int)c0, m, d->stage);
-    else
-      macro_kernel<float><<<(m + 255) / 256, 256, 0, d->stream>>>(
-          (const float*)d->buf[d->cur], d->flags, d->stride, (int)c0, m, d->stage);
+    const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
+    with_storage(d->p.storage, [&](auto tag) {
+      using S = decltype(tag);
+      macro_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
+          (const S*)d->buf[d->cur], d->flags, d->stride, d->sigma, (int)c0, cnt, d->stage);
+      return 0;
+    });
     HIP_OK(d, hipGetLastError());
-    HIP_OK(d, hipMemcpyAsync(host.data(), d->stage, (size_t)m * 4 * 8, hipMemcpyDeviceToHost,
+    HIP_OK(d, hipMemcpyAsync(host.data(), d->stage, (size_t)cnt * 4 * 8, hipMemcpyDeviceToHost,
                              d->stream));
     HIP_OK(d, hipStreamSynchronize(d->stream));
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < cnt; ++i) {
       if (drho) drho[c0 + i] = host[i];
       if (u) {
-        u[c0 + i] = host[m + i];
-        u[n + c0 + i] = host[2 * m + i];
-        u[2 * n + c0 + i] = host[3 * m + i];
+        u[c0 + i] = host[cnt + i];
+        u[n + c0 + i] = host[2 * cnt + i];
+        u[2 * n + c0 + i] = host[3 * cnt + i];
       }
     }
   }
@@ -659,26 +750,20 @@ LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   if (!F) return fail(d, LBM_ERR_INVALID_ARG, "F is NULL");
   const StepParams sp = step_params(d);
   const bool cli = d->p.wall == LBM_WALL_CLI;
-  if (d->p.storage == LBM_FP64) {
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
     if (cli)
-      drag_kernel<double, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-          (const double*)d->buf[d->cur], d->flags, sp, d->partials);
+      drag_kernel<S, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const S*)d->buf[d->cur], d->flags, sp, d->partials);
     else
-      drag_kernel<double, kSBB><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-          (const double*)d->buf[d->cur], d->flags, sp, d->partials);
-  } else {
-    if (cli)
-      drag_kernel<float, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-          (const float*)d->buf[d->cur], d->flags, sp, d->partials);
-    else
-      drag_kernel<float, kSBB><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-          (const float*)d->buf[d->cur], d->flags, sp, d->partials);
-  }
-  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, -1, d->result);
-  HIP_OK(d, hipGetLastError());
+      drag_kernel<S, kSBB><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+          (const S*)d->buf[d->cur], d->flags, sp, d->partials);
+    return 0;
+  });
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 0, d->result);
   double v[kRedVals];
-  HIP_OK(d, hipMemcpyAsync(v, d->result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
-  HIP_OK(d, hipStreamSynchronize(d->stream));
+  st = fetch_result(d, v);
+  if (st != LBM_OK) return st;
   F[0] = v[0];
   F[1] = v[1];
   F[2] = v[2];

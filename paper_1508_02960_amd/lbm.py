@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 COLLISIONS = {"srt": 0, "trt": 1, "mrt": 2}
 WALLS = {"sbb": 0, "cli": 1}
-STORAGES = {"fp64": 0, "fp32": 1}
+STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp16_rne": 4, "bf16_rne": 5}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device error", 4: "unstable",
           5: "not converged", 6: "invalid state"}
@@ -59,7 +59,8 @@ class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_fluid", C.c_int64), ("n_links", C.c_int64),
                 ("n_fallback", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("plane_stride", C.c_int64), ("nu", C.c_double), ("omega_plus", C.c_double),
-                ("omega_minus", C.c_double), ("bytes_per_fluid_update", C.c_int64)]
+                ("omega_minus", C.c_double), ("bytes_per_fluid_update", C.c_int64),
+                ("storage_scale", C.c_double)]
 
 
 _lib = None
@@ -237,6 +238,10 @@ class Domain:
         g = np.zeros((19,) + self.shape)
         self._check(library().lbm_get_state(self._h, _ptr(g)))
         return g
+
+    def refresh_info(self) -> Info:
+        self._check(library().lbm_get_info(self._h, C.byref(self.info)))
+        return self.info
 
     def step(self, n: int = 1) -> None:
         self._check(library().lbm_step(self._h, int(n)))

@@ -1,0 +1,112 @@
+"""16-bit storage of the deviations (FP16 / BF16, FP32 arithmetic, FP64
+reductions) against the FP64 oracle and the FP64 GPU path.
+
+Tolerances come from the formats: a stored value differs from the exact one
+by less than one spacing of the format (stochastic rounding) or half a
+spacing (round to nearest), and the spacing is at most 2^-10 (FP16) or 2^-7
+(BF16) of the value.  Permeability: at most 1e-3 relative to FP64.
+"""
+import numpy as np
+import pytest
+
+from paper_1508_02960_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+SPACING = {"fp16": 2.0 ** -10, "bf16": 2.0 ** -7, "fp16_rne": 2.0 ** -11, "bf16_rne": 2.0 ** -8}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.library()
+
+
+def rel(a, b, fluid):
+    a = a[..., fluid]
+    b = b[..., fluid]
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("storage", list(SPACING))
+@pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
+def test_one_step_within_format_spacing(orc, storage, collision):
+    """The state the GPU actually holds (read back) stepped by the oracle in
+    FP64 equals the GPU step up to the rounding of the stored result (one
+    spacing) plus that of the stored CLI coefficient a (half a spacing of a,
+    multiplying a difference of two populations: at most one more spacing)."""
+    shape = (11, 13, 70)
+    sp = inputs.random_spheres(shape, 6, (1.5, 4.0), seed=21)
+    kw = dict(tau=0.7, magic=0.21, delta_rho=3e-3, collision=collision, wall="cli", spheres=sp)
+    d = lbm.Domain(shape, storage=storage, **kw)
+    d.set_state(inputs.random_populations(shape, 1e-3, seed=22))
+    g_held = d.get_state()
+    o = orc.Oracle(shape, **kw)
+    o.set_state(g_held)
+    o.step(1)
+    d.step(1)
+    r = rel(d.get_state(), o.g, o.mask == 0)
+    assert r < 2 * SPACING[storage] + 1e-5, r
+    d.close()
+
+
+def _stokes_K(storage, shape, D, wall, drho, steps):
+    d = lbm.Domain(shape, tau=0.8, magic=3 / 16, delta_rho=drho, collision="trt", wall=wall,
+                   storage=storage, spheres=inputs.centred_sphere(shape, D))
+    s0 = d.refresh_info().storage_scale
+    d.run_to_residual(0.0, steps)
+    K, _ = d.permeability()
+    s1 = d.refresh_info().storage_scale
+    d.close()
+    return K, s0, s1
+
+
+@pytest.mark.parametrize("case", [((32, 32, 32), 24.0, "sbb", 2.15e-6, 6000),
+                                  ((64, 64, 64), 50.0, "cli", 1e-7, 12000)],
+                         ids=["sc32-sbb", "sc64-cli"])
+def test_stokes_permeability_16bit(case):
+    """K_D with stochastically rounded FP16/BF16 storage within 1e-3 of FP64
+    after the same steps from rest; round-to-nearest FP16 is off by more
+    (negative control).  FP16 starts with its scale set from delta_rho and
+    moves it as the flow develops."""
+    shape, D, wall, drho, steps = case
+    K64, _, _ = _stokes_K("fp64", *case)
+    K16, s0, s1 = _stokes_K("fp16", *case)
+    Kb, _, _ = _stokes_K("bf16", *case)
+    assert abs(K16 / K64 - 1) < 1e-3, K16 / K64 - 1
+    assert abs(Kb / K64 - 1) < 1e-3, Kb / K64 - 1
+    assert s1 != s0  # the FP16 scale was moved at the checks
+    Kr, _, _ = _stokes_K("fp16_rne", *case)
+    assert abs(Kr / K64 - 1) > 1e-3
+
+
+def test_stochastic_rounding_is_reproducible():
+    shape = (16, 16, 24)
+    sp = inputs.random_spheres(shape, 3, (2.0, 4.0), seed=91)
+    outs = []
+    for _ in range(2):
+        d = lbm.Domain(shape, tau=0.8, delta_rho=1e-3, wall="cli", spheres=sp, storage="fp16")
+        d.step(40)
+        outs.append(d.get_state())
+        d.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fp16_rescale_keeps_state():
+    """A run whose magnitude grows past the FP16 band is rescaled by powers of
+    two at the checks; the decoded state stays close to the FP32 run."""
+    shape = (24, 24, 24)
+    kw = dict(tau=0.9, magic=3 / 16, delta_rho=1e-4, wall="cli",
+              spheres=inputs.centred_sphere(shape, 16.0), check_interval=20)
+    a = lbm.Domain(shape, storage="fp16", **kw)
+    b = lbm.Domain(shape, storage="fp32", **kw)
+    a.run_to_residual(0.0, 400)
+    b.run_to_residual(0.0, 400)
+    _, ua = a.macroscopic()
+    _, ub = b.macroscopic()
+    fluid = a.mask() == 0
+    assert rel(ua, ub, fluid) < 5e-3
+    a.close()
+    b.close()
