@@ -194,6 +194,56 @@ lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x);
  * value given by the wall rule. */
 lbm_status lbm_drag(lbm_domain d, double F[3]);
 
+/* ------------------------------------------------------------------ batches
+ * A batch holds n_cells independent periodic cells of the same nx x ny x nz,
+ * each with its own solid geometry, relaxation time, magic parameter and
+ * pressure drop.  The cells are stacked along z: host arrays of a batch are
+ * laid out as for one domain of nx x ny x (n_cells nz) (cell b occupies z in
+ * [b nz, (b+1) nz)), but streaming wraps within each cell.  One launch steps
+ * every cell; lbm_run_to_residual tests each cell on the device every
+ * check_interval steps and drops converged, unstable or finished cells from
+ * later launches, so a run is a replayed graph of kernels with no host
+ * decision inside.  lbm_init_equilibrium, lbm_set_state, lbm_get_state,
+ * lbm_macroscopic and lbm_step act on the whole stack; lbm_mean_velocity,
+ * lbm_permeability, lbm_drag and lbm_set_delta_rho are per-domain and
+ * return LBM_ERR_STATE for a batch (use lbm_batch_results).  Storage must be
+ * FP32 or FP64. */
+typedef struct {
+  double tau;       /* > 1/2 */
+  double magic;     /* TRT Lambda in (0, 3/4] */
+  double delta_rho; /* density jump across the cell's x-periodic plane */
+} lbm_cell_params;
+
+/* Create a batch on the host.  common gives nx, ny, nz (of one cell),
+ * collision, wall, storage and check_interval (its tau, magic and delta_rho
+ * are ignored).  Geometry per cell: either masks (host uint8, n_cells
+ * consecutive cell masks) or spheres with sphere_counts[n_cells] (spheres of
+ * cell 0 first, then cell 1, ...; each cell needs at least one).  cells:
+ * n_cells parameter records.  Errors as lbm_create_domain, per cell. */
+lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks, const lbm_sphere* spheres,
+                            const int32_t* sphere_counts, const lbm_cell_params* cells,
+                            const lbm_params* common, lbm_domain* out);
+
+/* Per-cell results of the last lbm_run_to_residual of a batch (host arrays
+ * of n_cells, any may be NULL): superficial velocity (3 per cell) and
+ * permeability K_D (eq. (Darcy)) at the cell's last check, steps taken,
+ * last residual, and status 0 running / 1 converged / 2 unstable /
+ * 3 step limit. */
+lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64_t* steps,
+                             double* residual, int32_t* status);
+
+/* Launch shape of the batch step: rows of cells per workgroup (by; the
+ * workgroup spans a full x row, by rows, up to 1024 threads) and z planes
+ * per workgroup (zper, a divisor of nz). */
+lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper);
+
+/* Time every admissible (by, zper) over `steps` steps each (after two
+ * warm-up steps) with HIP events on the domain's stream, keep the fastest,
+ * and return it with its time per step in ms.  The state is reset to rest
+ * afterwards. */
+lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by, int32_t* zper,
+                              double* ms_per_step);
+
 /* Change the pressure drop of a bound domain (state kept). */
 lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho);
 

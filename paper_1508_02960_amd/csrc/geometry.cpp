@@ -102,6 +102,7 @@ bool build_geometry(const uint8_t* mask_in, const lbm_sphere* spheres, int ns, i
   g.nx = nx;
   g.ny = ny;
   g.nz = nz;
+  g.nz_cell = nz;
   g.ncell = (int64_t)nx * ny * nz;
   g.mask.assign(g.ncell, 0);
   if (mask_in) {
@@ -167,6 +168,26 @@ bool build_geometry(const uint8_t* mask_in, const lbm_sphere* spheres, int ns, i
     for (uint8_t b : fbs[z]) g.n_fallback += b;
   }
   return true;
+}
+
+void append_cell(Geometry& g, const Geometry& c) {
+  const int64_t off = g.ncell;
+  if (g.ncell == 0) {
+    g.nx = c.nx;
+    g.ny = c.ny;
+    g.nz = 0;
+    g.nz_cell = c.nz;
+  }
+  g.nz += c.nz;
+  g.ncell += c.ncell;
+  g.n_fluid += c.n_fluid;
+  g.n_fallback += c.n_fallback;
+  g.mask.insert(g.mask.end(), c.mask.begin(), c.mask.end());
+  g.flags.insert(g.flags.end(), c.flags.begin(), c.flags.end());
+  for (int64_t cell : c.link_cell) g.link_cell.push_back(cell + off);
+  g.link_dir.insert(g.link_dir.end(), c.link_dir.begin(), c.link_dir.end());
+  g.link_q.insert(g.link_q.end(), c.link_q.begin(), c.link_q.end());
+  g.link_fallback.insert(g.link_fallback.end(), c.link_fallback.begin(), c.link_fallback.end());
 }
 
 }  // namespace lbm

@@ -13,6 +13,7 @@ namespace lbm {
 
 struct Geometry {
   int nx = 0, ny = 0, nz = 0;
+  int nz_cell = 0;  // z period: nz for one domain, the cell edge for a batch
   int64_t ncell = 0, n_fluid = 0, n_fallback = 0;
   std::vector<uint8_t> mask;    // 1 = solid
   std::vector<uint32_t> flags;  // see lattice.hpp
@@ -27,5 +28,9 @@ struct Geometry {
 // geometry error (no fluid cell, bad sphere).
 bool build_geometry(const uint8_t* mask, const lbm_sphere* spheres, int n_spheres, int nx,
                     int ny, int nz, Geometry& g, std::string& err);
+
+// Append cell geometry `c` (one periodic cell) to the stacked batch `g`
+// (cells stacked along z).
+void append_cell(Geometry& g, const Geometry& c);
 
 }  // namespace lbm

@@ -530,6 +530,172 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
   }
 }
 
+// ------------------------------------------------------------ batches of cells
+// B independent periodic cells of nx x ny x nz are stacked along z (cell b
+// occupies cells [b*cell_size, (b+1)*cell_size) of every direction plane).
+// Each block covers zper consecutive z planes of one cell (zper divides nz),
+// reads that cell's parameters from a device table and skips inactive
+// (converged or stopped) cells.  Block ids of cell b are contiguous, so the
+// partial sums of a cell form one segment.
+
+template <typename S, int COLL, int WALL, bool RED>
+__global__ __launch_bounds__(1024) void batch_step_kernel(
+    const S* __restrict__ src, S* __restrict__ dst, const uint32_t* __restrict__ flags,
+    const StepParams* __restrict__ cells, const int* __restrict__ active, int nz_cell,
+    long long cell_size, int zper, double* __restrict__ partials) {
+  using C = typename ComputeOf<S>::type;
+  const int zz0 = blockIdx.z * zper;
+  const int b = zz0 / nz_cell;
+  if (!active[b]) return;
+  const StepParams p = cells[b];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool inside = x < p.nx && y < p.ny;
+  const long long off = (long long)b * cell_size;
+  const S* s = src + off;
+  S* d = dst + off;
+  const uint32_t* f = flags + off;
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < zper; ++i) {
+    const int z = zz0 + i - b * nz_cell;
+    const int c = x + p.nx * y + p.nx * p.ny * z;
+    const uint32_t fl = inside ? f[c] : kSolid;
+    if (fl & kSolid) continue;
+    C mom[5];
+    update_node<S, COLL, WALL>(s, d, p, x, y, z, c, fl, mom);
+    if constexpr (RED) {
+      const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
+      const double u2 = ux * ux + uy * uy + uz * uz;
+      v[0] += ux;
+      v[1] += uy;
+      v[2] += uz;
+      v[3] += rho;
+      if (isfinite(u2) && isfinite(rho))
+        v[4] = fmax(v[4], u2);
+      else
+        v[5] += 1.0;
+    }
+  }
+  if constexpr (RED) {
+    const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
+    const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    block_reduce<kRedVals>(v, kind, partials + blk * kRedVals);
+  }
+}
+
+// Per-cell convergence record, updated on the device at every check.
+struct CellStatus {
+  double prev_u;   // U_x at the previous check
+  double u[3];     // superficial velocity at the last check
+  double res;      // relative change of U_x over the last interval
+  double max_u2;   // largest |u|^2 at the last check
+  long long steps; // steps taken by the cell
+  int below;       // consecutive checks below tol
+  int status;      // 0 running, 1 converged, 2 unstable, 3 step limit
+  int parity;      // buffer holding the cell's final state (when stopped)
+  int pad;
+};
+
+// One block per cell folds that cell's segment of block partials (fixed
+// order) into results[b].
+__global__ __launch_bounds__(kRedThreads) void cell_reduce_kernel(const double* __restrict__ partials,
+                                                                  long long blocks_per_cell,
+                                                                  const int* __restrict__ active,
+                                                                  double* __restrict__ results) {
+  const int b = blockIdx.x;
+  if (!active[b]) return;
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
+  const double* in = partials + (long long)b * blocks_per_cell * kRedVals;
+  for (long long i = threadIdx.x; i < blocks_per_cell; i += kRedThreads)
+#pragma unroll
+    for (int j = 0; j < kRedVals; ++j)
+      v[j] = kind[j] ? fmax(v[j], in[i * kRedVals + j]) : v[j] + in[i * kRedVals + j];
+  block_reduce<kRedVals>(v, kind, results + (long long)b * kRedVals);
+}
+
+// Convergence test of every running cell after a check step (one block):
+// residual |U - U_prev| / |U| below tol three times in a row -> converged;
+// non-finite or |u| above the sound speed -> unstable; step limit -> stop.
+// active[b] and the count of running cells are rewritten.
+__global__ __launch_bounds__(1024) void batch_check_kernel(const double* __restrict__ results,
+                                                           CellStatus* __restrict__ st,
+                                                           int* __restrict__ active,
+                                                           int* __restrict__ n_active, int n_cells,
+                                                           double inv_cell_size, double tol,
+                                                           long long max_steps, int interval,
+                                                           int parity_now) {
+  __shared__ int count[32];
+  int mine = 0;
+  for (int b = threadIdx.x; b < n_cells; b += blockDim.x) {
+    CellStatus c = st[b];
+    if (c.status == 0) {
+      c.steps += interval;
+      const double* r = results + (long long)b * kRedVals;
+      const double U = r[0] * inv_cell_size;
+      c.u[0] = U;
+      c.u[1] = r[1] * inv_cell_size;
+      c.u[2] = r[2] * inv_cell_size;
+      c.max_u2 = r[4];
+      if (r[5] > 0 || !isfinite(U) || r[4] > 1.0 / 3.0) {
+        c.status = 2;
+      } else {
+        c.res = U != 0.0 ? fabs(U - c.prev_u) / fabs(U) : (U == c.prev_u ? 0.0 : INFINITY);
+        c.prev_u = U;
+        c.below = c.res < tol ? c.below + 1 : 0;
+        if (c.below >= 3) c.status = 1;
+        else if (c.steps >= max_steps) c.status = 3;
+      }
+      if (c.status != 0) c.parity = parity_now;
+      st[b] = c;
+    }
+    active[b] = c.status == 0;
+    mine += c.status == 0;
+  }
+  // block sum of running cells (wavefront shuffles, then LDS)
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_down(mine, off, 64);
+  if ((threadIdx.x & 63) == 0) count[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += count[w];
+    *n_active = t;
+  }
+}
+
+// Start of a batch run: every cell running, counters cleared.
+__global__ void batch_reset_kernel(CellStatus* __restrict__ st, int* __restrict__ active,
+                                   int n_cells, int parity) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_cells) return;
+  CellStatus c{};
+  c.res = INFINITY;
+  c.parity = parity;
+  st[b] = c;
+  active[b] = 1;
+}
+
+__global__ void fill_int_kernel(int* __restrict__ a, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Copy each stopped cell's final state into buffer `to` when it stopped in
+// the other buffer (so that the whole batch is read from one buffer).
+template <typename S>
+__global__ void batch_align_kernel(S* __restrict__ to, const S* __restrict__ from,
+                                   const CellStatus* __restrict__ st, int to_parity,
+                                   long long cell_size, long long stride, int n_cells) {
+  const long long total = (long long)n_cells * cell_size;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / cell_size);
+    if (st[b].status == 0 || st[b].parity == to_parity) continue;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) to[k * stride + i] = from[k * stride + i];
+  }
+}
+
 // Fold n partial vectors into gridDim.x vectors: block b takes a contiguous
 // chunk in a fixed order.
 __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const double* __restrict__ in,

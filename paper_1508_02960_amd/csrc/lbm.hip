@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -48,9 +50,22 @@ struct lbm_domain_s {
   // replayable launch sequences: kGraphSteps steps starting from buffer p
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  // batches of independent cells (0: one domain)
+  int batch = 0;
+  long long cell_size = 0;            // cells per batch cell
+  std::vector<lbm_cell_params> cellp;  // per-cell tau, Lambda, delta_rho
+  int bby = 0, zper = 1;              // batch launch shape: rows per block, z planes per block
+  StepParams* d_cells = nullptr;
+  int* d_active = nullptr;      // cells stepped in a residual run
+  int* d_active_all = nullptr;  // all ones, for lbm_step
+  CellStatus* d_status = nullptr;
+  double* d_results = nullptr;
+  int* d_nactive = nullptr;
+  std::vector<CellStatus> status_host;
   // layout offsets
   size_t off_buf[2] = {0, 0}, off_flags = 0, off_slot = 0, off_coef = 0, off_part = 0,
-         off_part2 = 0, off_res = 0, off_stage = 0, total = 0;
+         off_part2 = 0, off_res = 0, off_stage = 0, off_cells = 0, off_active = 0,
+         off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, total = 0;
 };
 
 namespace {
@@ -135,6 +150,12 @@ void layout(lbm_domain d) {
   o += align256(std::max<size_t>(nl, 1) * 8);
   const dim3 sg = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
   d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
+  if (d->batch) {
+    // most blocks: one row and one z plane per block
+    const long long bx = std::min(512, ((d->geo.nx + 63) / 64) * 64);
+    d->n_partials = std::max<long long>(
+        d->n_partials, ((d->geo.nx + bx - 1) / bx) * (long long)d->geo.ny * d->geo.nz);
+  }
   d->off_part = o;
   o += align256((size_t)d->n_partials * kRedVals * 8);
   d->off_part2 = o;
@@ -146,6 +167,19 @@ void layout(lbm_domain d) {
   d->stage_cells = std::min<size_t>(d->stage_cells, (size_t)n);
   d->off_stage = o;
   o += align256(d->stage_cells * 4 * 8);
+  const size_t nb = (size_t)std::max(d->batch, 1);
+  d->off_cells = o;
+  o += align256(nb * sizeof(StepParams));
+  d->off_active = o;
+  o += align256(nb * sizeof(int));
+  d->off_active_all = o;
+  o += align256(nb * sizeof(int));
+  d->off_status = o;
+  o += align256(nb * sizeof(CellStatus));
+  d->off_results = o;
+  o += align256(nb * kRedVals * sizeof(double));
+  d->off_nactive = o;
+  o += align256(sizeof(int));
   d->total = o;
 }
 
@@ -270,6 +304,264 @@ lbm_status enqueue_steps(lbm_domain d, int64_t n) {
   }
   HIP_OK(d, hipGetLastError());
   return LBM_OK;
+}
+
+// ---- batches
+
+dim3 batch_block(lbm_domain d) {
+  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
+  return dim3(bx, d->bby, 1);
+}
+dim3 batch_grid(lbm_domain d) {
+  const dim3 b = batch_block(d);
+  return dim3((d->geo.nx + b.x - 1) / b.x, (d->geo.ny + b.y - 1) / b.y,
+              (unsigned)((long long)d->batch * d->geo.nz_cell / d->zper));
+}
+
+template <typename S, bool RED>
+const void* batch_fn(int collision, int wall) {
+  switch (collision * 2 + wall) {
+    case 0: return (const void*)batch_step_kernel<S, kSRT, kSBB, RED>;
+    case 1: return (const void*)batch_step_kernel<S, kSRT, kCLI, RED>;
+    case 2: return (const void*)batch_step_kernel<S, kTRT, kSBB, RED>;
+    case 3: return (const void*)batch_step_kernel<S, kTRT, kCLI, RED>;
+    case 4: return (const void*)batch_step_kernel<S, kMRT, kSBB, RED>;
+    default: return (const void*)batch_step_kernel<S, kMRT, kCLI, RED>;
+  }
+}
+
+const void* batch_function(lbm_domain d, bool red) {
+  if (d->p.storage == LBM_FP64)
+    return red ? batch_fn<double, true>(d->p.collision, d->p.wall)
+               : batch_fn<double, false>(d->p.collision, d->p.wall);
+  return red ? batch_fn<float, true>(d->p.collision, d->p.wall)
+             : batch_fn<float, false>(d->p.collision, d->p.wall);
+}
+
+// Kernel-node or launch arguments of one batch step from buffer `from`.
+struct BatchArgs {
+  const void* src;
+  void* dst;
+  const uint32_t* flags;
+  const StepParams* cells;
+  const int* active;
+  int nz_cell;
+  long long cell_size;
+  int zper;
+  double* partials;
+  void* ptrs[9];
+  void fill(lbm_domain d, int from, const int* act) {
+    src = d->buf[from];
+    dst = d->buf[1 - from];
+    flags = d->flags;
+    cells = d->d_cells;
+    active = act;
+    nz_cell = d->geo.nz_cell;
+    cell_size = d->cell_size;
+    zper = d->zper;
+    partials = d->partials;
+    ptrs[0] = &src;
+    ptrs[1] = &dst;
+    ptrs[2] = &flags;
+    ptrs[3] = &cells;
+    ptrs[4] = &active;
+    ptrs[5] = &nz_cell;
+    ptrs[6] = &cell_size;
+    ptrs[7] = &zper;
+    ptrs[8] = &partials;
+  }
+};
+
+lbm_status launch_batch_step(lbm_domain d, bool red, const int* act) {
+  BatchArgs a;
+  a.fill(d, d->cur, act);
+  HIP_OK(d, hipLaunchKernel(batch_function(d, red), batch_grid(d), batch_block(d), a.ptrs, 0,
+                            d->stream));
+  d->cur = 1 - d->cur;
+  ++d->step_count;
+  return LBM_OK;
+}
+
+lbm_status enqueue_batch_steps(lbm_domain d, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) {
+    lbm_status st = launch_batch_step(d, false, d->d_active_all);
+    if (st != LBM_OK) return st;
+  }
+  HIP_OK(d, hipGetLastError());
+  return LBM_OK;
+}
+
+// Graph of `reps` check intervals of `interval` steps starting from buffer
+// `from`: (interval - 1) steps, one step with block partials, the per-cell
+// fold and the device-side convergence test.  Kernel nodes only.
+lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, double tol,
+                             long long max_steps, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIP_OK(d, hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  auto add = [&](const void* fn, dim3 grid, dim3 block, void** args) -> hipError_t {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  const dim3 grid = batch_grid(d), block = batch_block(d);
+  const long long blocks_per_cell =
+      (long long)grid.x * grid.y * ((long long)d->geo.nz_cell / d->zper);
+  int parity = from;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    for (int i = 0; i < interval && e == hipSuccess; ++i) {
+      const bool red = i == interval - 1;
+      BatchArgs a;
+      a.fill(d, parity, d->d_active);
+      e = add(batch_function(d, red), grid, block, a.ptrs);
+      parity = 1 - parity;
+    }
+    if (e != hipSuccess) break;
+    const double* part = d->partials;
+    long long bpc = blocks_per_cell;
+    const int* act = d->d_active;
+    double* res = d->d_results;
+    void* rargs[] = {(void*)&part, (void*)&bpc, (void*)&act, (void*)&res};
+    e = add((const void*)cell_reduce_kernel, dim3(d->batch), dim3(kRedThreads), rargs);
+    if (e != hipSuccess) break;
+    const double* resc = d->d_results;
+    CellStatus* st = d->d_status;
+    int* actw = d->d_active;
+    int* nact = d->d_nactive;
+    int ncells = d->batch;
+    double inv = 1.0 / (double)d->cell_size;
+    double t = tol;
+    long long ms = max_steps;
+    int iv = interval;
+    int pn = parity;
+    void* cargs[] = {(void*)&resc, (void*)&st,  (void*)&actw, (void*)&nact, (void*)&ncells,
+                     (void*)&inv,  (void*)&t,   (void*)&ms,   (void*)&iv,   (void*)&pn};
+    e = add((const void*)batch_check_kernel, dim3(1), dim3(1024), cargs);
+  }
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(d, LBM_ERR_DEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess)
+    return fail(d, LBM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  *out = ex;
+  return LBM_OK;
+}
+
+// Optional progress line on stderr (environment LBM_PROGRESS set), at most
+// every 10 s, for long device-side loops.
+void report_progress(lbm_domain d, int64_t steps, int running) {
+  static const bool on = std::getenv("LBM_PROGRESS") != nullptr;
+  if (!on) return;
+  static auto last = std::chrono::steady_clock::now();
+  const auto now = std::chrono::steady_clock::now();
+  if (now - last < std::chrono::seconds(10)) return;
+  last = now;
+  std::fprintf(stderr, "[lbm] %s: %lld steps, %d running\n", d->batch ? "batch" : "domain",
+               (long long)steps, running);
+  std::fflush(stderr);
+}
+
+// Per-cell step parameters into the device table (relaxation rates from
+// each cell's tau and Lambda, Sec. 2.1; jump from its delta_rho).
+lbm_status upload_cell_params(lbm_domain d) {
+  std::vector<StepParams> t(d->batch);
+  for (int b = 0; b < d->batch; ++b) {
+    const lbm_cell_params& c = d->cellp[b];
+    StepParams& sp = t[b];
+    sp.nx = d->geo.nx;
+    sp.ny = d->geo.ny;
+    sp.nz = d->geo.nz_cell;
+    sp.stride = d->stride;
+    sp.jump_axis = (1.0 / 18.0) * c.delta_rho;
+    sp.jump_diag = (1.0 / 36.0) * c.delta_rho;
+    sp.omega_p = 1.0 / c.tau;
+    sp.omega_m = d->p.collision == LBM_TRT ? 1.0 / (0.5 + c.magic / (c.tau - 0.5)) : sp.omega_p;
+    sp.s_e = 1.0 / (0.5 + (c.tau - 0.5) / 4.6);
+    sp.s_zeta = 8.0 * (2.0 - sp.omega_p) / (8.0 - sp.omega_p);
+    sp.sigma = 1.0;
+    sp.seed = 0;
+  }
+  HIP_OK(d, hipMemcpyAsync(d->d_cells, t.data(), t.size() * sizeof(StepParams),
+                           hipMemcpyHostToDevice, d->stream));
+  return LBM_OK;
+}
+
+lbm_status batch_run(lbm_domain d, double tol, int64_t max_steps, int64_t* steps_done,
+                     double* residual) {
+  const int m = d->p.check_interval;
+  const int reps = std::max(1, 512 / m);
+  batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_status, d->d_active,
+                                                                    d->batch, d->cur);
+  HIP_OK(d, hipGetLastError());
+  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  lbm_status st = LBM_OK;
+  int64_t done = 0;
+  int nact = d->batch;
+  while (done < max_steps && nact > 0) {
+    if (!ex[d->cur]) {
+      st = build_batch_graph(d, d->cur, reps, m, tol, (long long)max_steps, &ex[d->cur]);
+      if (st != LBM_OK) break;
+    }
+    hipError_t e = hipGraphLaunch(ex[d->cur], d->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&nact, d->d_nactive, sizeof(int), hipMemcpyDeviceToHost, d->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+    if (e != hipSuccess) {
+      st = fail(d, LBM_ERR_DEVICE, std::string("batch run: ") + hipGetErrorString(e));
+      break;
+    }
+    const int64_t n = (int64_t)reps * m;
+    done += n;
+    if (n & 1) d->cur = 1 - d->cur;
+    d->step_count += n;
+    report_progress(d, done, nact);
+  }
+  for (int i = 0; i < 2; ++i)
+    if (ex[i]) (void)hipGraphExecDestroy(ex[i]);
+  if (st != LBM_OK) return st;
+  // every cell's final state into buffer cur
+  if (d->p.storage == LBM_FP64)
+    batch_align_kernel<double><<<2048, 256, 0, d->stream>>>(
+        (double*)d->buf[d->cur], (const double*)d->buf[1 - d->cur], d->d_status, d->cur,
+        d->cell_size, d->stride, d->batch);
+  else
+    batch_align_kernel<float><<<2048, 256, 0, d->stream>>>(
+        (float*)d->buf[d->cur], (const float*)d->buf[1 - d->cur], d->d_status, d->cur,
+        d->cell_size, d->stride, d->batch);
+  HIP_OK(d, hipGetLastError());
+  d->status_host.resize(d->batch);
+  HIP_OK(d, hipMemcpyAsync(d->status_host.data(), d->d_status, d->batch * sizeof(CellStatus),
+                           hipMemcpyDeviceToHost, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  int64_t smax = 0;
+  double rmax = 0.0;
+  bool unstable = false, all_conv = true;
+  for (const CellStatus& c : d->status_host) {
+    smax = std::max<int64_t>(smax, c.steps);
+    rmax = std::max(rmax, c.res);
+    unstable |= c.status == 2;
+    all_conv &= c.status == 1;
+  }
+  if (steps_done) *steps_done = smax;
+  if (residual) *residual = rmax;
+  if (unstable) {
+    d->err = "at least one cell became unstable";
+    return LBM_ERR_UNSTABLE;
+  }
+  return all_conv ? LBM_OK : LBM_ERR_NOT_CONVERGED;
 }
 
 lbm_status fetch_result(lbm_domain d, double* vals) {
@@ -483,6 +775,19 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->partials2 = (double*)(d->ws + d->off_part2);
   d->result = (double*)(d->ws + d->off_res);
   d->stage = (double*)(d->ws + d->off_stage);
+  d->d_cells = (StepParams*)(d->ws + d->off_cells);
+  d->d_active = (int*)(d->ws + d->off_active);
+  d->d_active_all = (int*)(d->ws + d->off_active_all);
+  d->d_status = (CellStatus*)(d->ws + d->off_status);
+  d->d_results = (double*)(d->ws + d->off_results);
+  d->d_nactive = (int*)(d->ws + d->off_nactive);
+  if (d->batch) {
+    lbm_status bst = upload_cell_params(d);
+    if (bst != LBM_OK) return bst;
+    fill_int_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_active_all, d->batch, 1);
+    batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_status, d->d_active,
+                                                                      d->batch, 0);
+  }
 
   const int64_t n = d->geo.ncell;
   HIP_OK(d, hipMemcpyAsync(d->flags, d->geo.flags.data(), n * 4, hipMemcpyHostToDevice,
@@ -492,13 +797,15 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   const size_t nl = d->geo.link_cell.size();
   std::vector<long long> slot(nl);
   std::vector<double> coef(nl);
-  const int nx = d->geo.nx, ny = d->geo.ny, nz = d->geo.nz;
+  const int nx = d->geo.nx, ny = d->geo.ny;
   for (size_t i = 0; i < nl; ++i) {
     const int64_t c = d->geo.link_cell[i];
     const int j = d->geo.link_dir[i];
     const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+    // z wraps within the periodic cell (the whole box for one domain)
+    const int zc = d->geo.nz_cell, z0 = z - z % zc;
     const int xs = (x + kLat.ex[j] + nx) % nx, ys = (y + kLat.ey[j] + ny) % ny,
-              zs = (z + kLat.ez[j] + nz) % nz;
+              zs = z0 + (z - z0 + kLat.ez[j] + zc) % zc;
     const int64_t s = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
     slot[i] = (long long)kLat.opp[j] * d->stride + s;
     const double q = d->geo.link_q[i];
@@ -632,7 +939,7 @@ LBM_API lbm_status lbm_step(lbm_domain d, int64_t n) {
   if (st != LBM_OK) return st;
   if (n < 0) return fail(d, LBM_ERR_INVALID_ARG, "n must be >= 0");
   if (d->unstable) return fail(d, LBM_ERR_STATE, "state is unstable; re-initialise first");
-  return enqueue_steps(d, n);
+  return d->batch ? enqueue_batch_steps(d, n) : enqueue_steps(d, n);
 }
 
 LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_steps,
@@ -641,6 +948,7 @@ LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_ste
   if (st != LBM_OK) return st;
   if (max_steps < 0 || !(tol >= 0)) return fail(d, LBM_ERR_INVALID_ARG, "bad tol or max_steps");
   if (d->unstable) return fail(d, LBM_ERR_STATE, "state is unstable; re-initialise first");
+  if (d->batch) return batch_run(d, tol, max_steps, steps_done, residual);
   const double cs2 = 1.0 / 3.0;
   const double ncell = (double)d->geo.ncell;
   double v[kRedVals];
@@ -673,6 +981,7 @@ LBM_API lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_ste
       out = LBM_OK;
       break;
     }
+    report_progress(d, done, 1);
   }
   if (steps_done) *steps_done = done;
   if (residual) *residual = res;
@@ -715,6 +1024,7 @@ LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_spee
                                      double* total_drho) {
   lbm_status st = check_ready(d);
   if (st != LBM_OK) return st;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
   double v[kRedVals];
   st = reduce_state(d, v);
   if (st != LBM_OK) return st;
@@ -734,6 +1044,7 @@ LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_spee
 LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x) {
   lbm_status st = check_ready(d);
   if (st != LBM_OK) return st;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
   if (d->p.delta_rho == 0.0) return fail(d, LBM_ERR_STATE, "delta_rho is zero");
   double U[3];
   st = lbm_mean_velocity(d, U, nullptr, nullptr);
@@ -747,6 +1058,7 @@ LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x) {
 LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   lbm_status st = check_ready(d);
   if (st != LBM_OK) return st;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
   if (!F) return fail(d, LBM_ERR_INVALID_ARG, "F is NULL");
   const StepParams sp = step_params(d);
   const bool cli = d->p.wall == LBM_WALL_CLI;
@@ -770,8 +1082,187 @@ LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   return LBM_OK;
 }
 
+// ------------------------------------------------------------------ batches
+
+LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
+                                    const lbm_sphere* spheres, const int32_t* sphere_counts,
+                                    const lbm_cell_params* cells, const lbm_params* common,
+                                    lbm_domain* out) {
+  g_create_error.clear();
+  if (!out) return LBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto bad = [](const std::string& m) {
+    g_create_error = m;
+    return LBM_ERR_INVALID_ARG;
+  };
+  if (n_cells < 1 || !cells || !common) return bad("n_cells >= 1, cells and common are required");
+  const lbm_params& p = *common;
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return bad("box edges must be >= 1");
+  const int64_t csize = (int64_t)p.nx * p.ny * p.nz;
+  if (csize * n_cells >= (int64_t(1) << 31)) return bad("n_cells*nx*ny*nz must be below 2^31");
+  if (p.ny > 65535 || (int64_t)p.nz * n_cells > 65535 * 64)
+    return bad("ny must be at most 65535 and n_cells*nz at most 65535*64");
+  if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
+  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_CLI) return bad("unknown wall rule");
+  if (p.storage != LBM_FP64 && p.storage != LBM_FP32) return bad("batches store FP32 or FP64");
+  if (p.check_interval < 0) return bad("check_interval must be >= 0");
+  if ((masks != nullptr) == (spheres != nullptr)) return bad("give exactly one of masks and spheres");
+  if (spheres && !sphere_counts) return bad("sphere_counts is required with spheres");
+  for (int b = 0; b < n_cells; ++b) {
+    const lbm_cell_params& c = cells[b];
+    if (!(c.tau > 0.5) || !std::isfinite(c.tau)) return bad("cell tau must be finite and > 1/2");
+    if (p.collision == LBM_TRT && !(c.magic > 0.0 && c.magic <= 0.75))
+      return bad("cell TRT magic parameter must lie in (0, 3/4]");
+    if (!std::isfinite(c.delta_rho)) return bad("cell delta_rho must be finite");
+  }
+  const double emin = std::min(p.nx, std::min(p.ny, p.nz));
+  if (spheres) {
+    int64_t at = 0;
+    for (int b = 0; b < n_cells; ++b) {
+      if (sphere_counts[b] < 1) return bad("every cell needs at least one sphere");
+      for (int i = 0; i < sphere_counts[b]; ++i) {
+        const lbm_sphere& q = spheres[at + i];
+        if (!(q.r > 0.0) || !(q.r < emin)) return bad("sphere radius must lie in (0, min edge)");
+        if (!(q.cx >= 0 && q.cx < p.nx && q.cy >= 0 && q.cy < p.ny && q.cz >= 0 && q.cz < p.nz))
+          return bad("sphere centre must lie inside the cell");
+      }
+      at += sphere_counts[b];
+    }
+  }
+  lbm_domain d = new (std::nothrow) lbm_domain_s();
+  if (!d) return bad("out of host memory");
+  d->p = p;
+  if (d->p.check_interval == 0) d->p.check_interval = 100;
+  d->batch = n_cells;
+  d->cell_size = csize;
+  d->cellp.assign(cells, cells + n_cells);
+  try {
+    int64_t at = 0;
+    for (int b = 0; b < n_cells; ++b) {
+      Geometry g;
+      std::string err;
+      const uint8_t* m = masks ? masks + (size_t)b * csize : nullptr;
+      const lbm_sphere* sp = spheres ? spheres + at : nullptr;
+      const int ns = spheres ? sphere_counts[b] : 0;
+      if (spheres) at += sphere_counts[b];
+      if (!build_geometry(m, sp, ns, p.nx, p.ny, p.nz, g, err)) {
+        delete d;
+        return bad("cell " + std::to_string(b) + ": " + err);
+      }
+      append_cell(d->geo, g);
+    }
+  } catch (const std::bad_alloc&) {
+    delete d;
+    return bad("out of host memory building the geometry");
+  }
+  d->nu = (cells[0].tau - 0.5) / 3.0;
+  d->omega_p = 1.0 / cells[0].tau;
+  d->omega_m = d->omega_p;
+  d->bby = std::max(1, 256 / std::min(1024, ((p.nx + 63) / 64) * 64));
+  d->zper = 1;
+  layout(d);
+  choose_sigma(d, 0.0);
+  *out = d;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64_t* steps,
+                                     double* residual, int32_t* status) {
+  if (!d || !d->batch) return LBM_ERR_INVALID_ARG;
+  if (d->status_host.size() != (size_t)d->batch)
+    return fail(d, LBM_ERR_STATE, "no residual run on this batch yet");
+  for (int b = 0; b < d->batch; ++b) {
+    const CellStatus& c = d->status_host[b];
+    if (U) {
+      U[3 * b] = c.u[0];
+      U[3 * b + 1] = c.u[1];
+      U[3 * b + 2] = c.u[2];
+    }
+    if (K_D) {
+      const lbm_cell_params& cp = d->cellp[b];
+      const double nu = (cp.tau - 0.5) / 3.0;
+      K_D[b] = cp.delta_rho != 0.0 ? nu * c.u[0] * d->geo.nx / (cp.delta_rho / 3.0) : NAN;
+    }
+    if (steps) steps[b] = c.steps;
+    if (residual) residual[b] = c.res;
+    if (status) status[b] = c.status;
+  }
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper) {
+  if (!d || !d->batch) return LBM_ERR_INVALID_ARG;
+  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
+  if (by < 1 || bx * by > 1024 || zper < 1 || d->geo.nz_cell % zper != 0)
+    return fail(d, LBM_ERR_INVALID_ARG, "by*row width must be <= 1024 and zper must divide nz");
+  d->bby = by;
+  d->zper = zper;
+  return LBM_OK;
+}
+
+// Rest state again after tuning: zero both buffers, re-scatter coefficients.
+static lbm_status reset_to_rest(lbm_domain d) {
+  void* ws = d->ws;
+  size_t bytes = d->ws_bytes;
+  hipStream_t stream = d->stream;
+  const int by = d->bby, zp = d->zper;
+  lbm_status st = lbm_bind(d, ws, bytes, stream);
+  d->bby = by;
+  d->zper = zp;
+  return st;
+}
+
+LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_out,
+                                      int32_t* zper_out, double* ms_out) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!d->batch) return fail(d, LBM_ERR_STATE, "autotune applies to batches");
+  if (steps < 1) return fail(d, LBM_ERR_INVALID_ARG, "steps must be >= 1");
+  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
+  hipEvent_t e0, e1;
+  HIP_OK(d, hipEventCreate(&e0));
+  HIP_OK(d, hipEventCreate(&e1));
+  double best = INFINITY;
+  int best_by = d->bby, best_z = d->zper;
+  for (int by = 1; by * bx <= 1024 && by <= d->geo.ny; by *= 2) {
+    for (int zp = 1; zp <= 8 && zp <= d->geo.nz_cell; zp *= 2) {
+      if (d->geo.nz_cell % zp) continue;
+      d->bby = by;
+      d->zper = zp;
+      st = enqueue_batch_steps(d, 2);
+      if (st != LBM_OK) break;
+      HIP_OK(d, hipEventRecord(e0, d->stream));
+      st = enqueue_batch_steps(d, steps);
+      if (st != LBM_OK) break;
+      HIP_OK(d, hipEventRecord(e1, d->stream));
+      HIP_OK(d, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OK(d, hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / steps;
+      if (per < best) {
+        best = per;
+        best_by = by;
+        best_z = zp;
+      }
+    }
+    if (st != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LBM_OK) return st;
+  d->bby = best_by;
+  d->zper = best_z;
+  st = reset_to_rest(d);
+  if (st != LBM_OK) return st;
+  if (by_out) *by_out = best_by;
+  if (zper_out) *zper_out = best_z;
+  if (ms_out) *ms_out = best;
+  return LBM_OK;
+}
+
 LBM_API lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho) {
   if (!d) return LBM_ERR_INVALID_ARG;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch");
   if (!std::isfinite(delta_rho)) return fail(d, LBM_ERR_INVALID_ARG, "delta_rho must be finite");
   d->p.delta_rho = delta_rho;
   drop_graphs(d);

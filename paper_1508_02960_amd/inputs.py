@@ -53,3 +53,17 @@ def random_velocity(shape, amplitude: float, seed: int) -> np.ndarray:
     """Velocity field u[3, nz, ny, nx] with i.i.d. components in [-amplitude, amplitude]."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-amplitude, amplitude, size=(3,) + tuple(shape))
+
+
+def batch_cell_draws(seed: int, edge: int = 64):
+    """Endless seeded draws for one-sphere cells: diameter U[40, 60] (scaled
+    by edge / 64), centre U[0, edge)^3, tau U[0.55, 1.0], log10 Re_p
+    U[-3, log10 300].  The caller decides which draws to keep."""
+    rng = np.random.default_rng(seed)
+    s = edge / 64.0
+    while True:
+        d = rng.uniform(40.0, 60.0) * s
+        c = rng.uniform(0.0, 1.0, size=3) * edge
+        tau = rng.uniform(0.55, 1.0)
+        log_re = rng.uniform(-3.0, np.log10(300.0))
+        yield dict(diameter=d, centre=c, tau=tau, re_p=10.0 ** log_re)

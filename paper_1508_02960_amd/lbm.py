@@ -26,7 +26,8 @@ EXPORTS = (
     "lbm_init_equilibrium", "lbm_set_state", "lbm_get_state", "lbm_step",
     "lbm_run_to_residual", "lbm_macroscopic", "lbm_mean_velocity", "lbm_permeability",
     "lbm_drag", "lbm_set_delta_rho", "lbm_synchronize", "lbm_destroy", "lbm_status_string",
-    "lbm_last_error",
+    "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
+    "lbm_batch_autotune",
 )
 
 
@@ -55,6 +56,10 @@ class Sphere(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double), ("r", C.c_double)]
 
 
+class CellParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("magic", C.c_double), ("delta_rho", C.c_double)]
+
+
 class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_fluid", C.c_int64), ("n_links", C.c_int64),
                 ("n_fallback", C.c_int64), ("workspace_bytes", C.c_int64),
@@ -73,6 +78,9 @@ def library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime; load it first so that liblbm.so binds
+    # to the same libamdhip64 instead of a second copy that sees no device
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER
@@ -94,6 +102,10 @@ def library():
         "lbm_set_delta_rho": [vp, d],
         "lbm_synchronize": [vp],
         "lbm_destroy": [vp],
+        "lbm_create_batch": [i32, vp, vp, vp, vp, P(Params), P(vp)],
+        "lbm_batch_results": [vp, vp, vp, vp, vp, vp],
+        "lbm_batch_set_shape": [vp, i32, i32],
+        "lbm_batch_autotune": [vp, i32, P(i32), P(i32), P(d)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -287,3 +299,99 @@ class Domain:
         F = np.zeros(3)
         self._check(library().lbm_drag(self._h, _ptr(F)))
         return F
+
+
+BATCH_STATUS = {0: "running", 1: "converged", 2: "unstable", 3: "step_limit"}
+
+
+class Batch(Domain):
+    """Independent periodic cells of one shape ``(nz, ny, nx)``, stepped together.
+
+    ``cells`` is a list of dicts with ``tau``, ``delta_rho``, optional
+    ``magic`` and either ``spheres`` (rows cx, cy, cz, r) or ``mask``.
+    Arrays of the whole batch have shape ``(n_cells, nz, ny, nx)`` (per
+    population or component in front).
+    """
+
+    def __init__(self, cell_shape, cells, *, collision: str = "trt", wall: str = "sbb",
+                 storage: str = "fp32", check_interval: int = 100, device=None,
+                 bind: bool = True):
+        lib = library()
+        self.cell_shape = tuple(int(v) for v in cell_shape)
+        nz, ny, nx = self.cell_shape
+        self.n_cells = len(cells)
+        self.shape = (self.n_cells * nz, ny, nx)
+        self.params = Params(nx, ny, nz, 0.0, 0.0, 0.0, COLLISIONS[collision], WALLS[wall],
+                             STORAGES[storage], int(check_interval))
+        self.storage = storage
+        self.cells = [dict(c) for c in cells]
+        cp = (CellParams * self.n_cells)(*[
+            CellParams(float(c["tau"]), float(c.get("magic", 3 / 16)), float(c["delta_rho"]))
+            for c in cells])
+        masks = None
+        sp = None
+        counts = None
+        if "mask" in cells[0]:
+            masks = np.ascontiguousarray(np.stack([c["mask"] for c in cells]), dtype=np.uint8)
+        else:
+            rows = [np.reshape(np.asarray(c["spheres"], np.float64), (-1, 4)) for c in cells]
+            allsp = np.concatenate(rows)
+            sp = (Sphere * len(allsp))(*[Sphere(*r) for r in allsp])
+            counts = np.array([len(r) for r in rows], np.int32)
+        h = C.c_void_p()
+        st = lib.lbm_create_batch(self.n_cells, _ptr(masks), sp, _ptr(counts), cp,
+                                  C.byref(self.params), C.byref(h))
+        if st != 0:
+            raise LbmError(st, lib.lbm_last_error(None).decode())
+        self._h = h
+        self._ws = None
+        self._stream = None
+        self.info = Info()
+        self._check(lib.lbm_get_info(self._h, C.byref(self.info)))
+        if bind:
+            self.bind(device)
+
+    def _as_batch(self, a):
+        return a.reshape(a.shape[:-3] + (self.n_cells,) + self.cell_shape)
+
+    def mask(self) -> np.ndarray:
+        return self._as_batch(super().mask())
+
+    def get_state(self) -> np.ndarray:
+        return self._as_batch(super().get_state())
+
+    def macroscopic(self):
+        drho, u = super().macroscopic()
+        return self._as_batch(drho), self._as_batch(u)
+
+    def init_equilibrium(self, drho0=None, u0=None) -> None:
+        d = None if drho0 is None else np.reshape(drho0, self.shape)
+        u = None if u0 is None else np.reshape(u0, (3,) + self.shape)
+        super().init_equilibrium(d, u)
+
+    def set_state(self, g) -> None:
+        super().set_state(np.reshape(g, (19,) + self.shape))
+
+    def set_shape(self, by: int, zper: int) -> None:
+        self._check(library().lbm_batch_set_shape(self._h, int(by), int(zper)))
+
+    def autotune(self, steps: int = 20):
+        by = C.c_int32()
+        zp = C.c_int32()
+        ms = C.c_double()
+        self._check(library().lbm_batch_autotune(self._h, int(steps), C.byref(by), C.byref(zp),
+                                                 C.byref(ms)))
+        return by.value, zp.value, ms.value
+
+    def results(self):
+        n = self.n_cells
+        U = np.zeros((n, 3))
+        K = np.zeros(n)
+        steps = np.zeros(n, np.int64)
+        res = np.zeros(n)
+        status = np.zeros(n, np.int32)
+        self._check(library().lbm_batch_results(self._h, _ptr(U), _ptr(K), _ptr(steps),
+                                                _ptr(res), _ptr(status)))
+        return dict(U=U, K_D=K, steps=steps, residual=res,
+                    status=[BATCH_STATUS[int(v)] for v in status])
+

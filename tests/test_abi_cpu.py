@@ -144,3 +144,29 @@ def test_mask_input_gives_half_distance():
     _, _, q, _ = d.links()
     assert len(q) > 0 and np.all(q == 0.5)
     d.close()
+
+
+def test_batch_creation_and_validation(orc):
+    shape = (8, 9, 10)
+    cells = [dict(spheres=inputs.random_spheres(shape, 2, (1.5, 3.0), seed=s), tau=0.7 + 0.1 * s,
+                  delta_rho=1e-4) for s in range(3)]
+    b = lbm.Batch(shape, cells, wall="cli", bind=False)
+    m = b.mask()
+    assert m.shape == (3,) + shape
+    for i, c in enumerate(cells):
+        assert np.array_equal(m[i], orc.voxelise(shape, c["spheres"]))
+    assert b.info.n_fluid == int((m == 0).sum())
+    # links of cell 1 are those of cell 1 alone, shifted by one cell
+    cell, dirs, q, fb = b.links()
+    ncell = int(np.prod(shape))
+    sel = (cell >= ncell) & (cell < 2 * ncell)
+    single = lbm.Domain(shape, tau=0.8, spheres=cells[1]["spheres"], wall="cli", bind=False)
+    c1, d1, q1, f1 = single.links()
+    assert np.array_equal(cell[sel] - ncell, c1) and np.array_equal(dirs[sel], d1)
+    assert np.array_equal(q[sel], q1) and np.array_equal(fb[sel], f1)
+    single.close()
+    b.close()
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch(shape, [dict(cells[0], tau=0.5)], bind=False)
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch(shape, cells, storage="fp16", bind=False)

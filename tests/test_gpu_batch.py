@@ -1,0 +1,120 @@
+"""Batches of independent cells (one launch per step, per-cell parameters,
+device-side convergence) against the oracle run cell by cell."""
+import numpy as np
+import pytest
+
+from paper_1508_02960_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.library()
+
+
+CELL = (12, 10, 14)
+
+
+def _cells(n, seed, drho_scale=1e-3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n):
+        sp = inputs.random_spheres(CELL, int(rng.integers(1, 4)), (1.5, 3.5), seed=seed * 100 + b)
+        out.append(dict(spheres=sp, tau=float(rng.uniform(0.6, 1.2)),
+                        magic=float(rng.uniform(0.1, 0.3)),
+                        delta_rho=float(rng.uniform(-1, 1) * drho_scale)))
+    return out
+
+
+def _oracle(orc, c, wall="cli", collision="trt"):
+    return orc.Oracle(CELL, tau=c["tau"], magic=c["magic"], delta_rho=c["delta_rho"],
+                      collision=collision, wall=wall, spheres=c["spheres"])
+
+
+@pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
+def test_batch_steps_match_cells(orc, collision):
+    """Each cell of a batch evolves exactly as the same cell alone (FP64):
+    per-cell parameters, z wrap inside the cell, wall coefficients."""
+    cells = _cells(4, seed=1)
+    b = lbm.Batch(CELL, cells, collision=collision, wall="cli", storage="fp64")
+    assert np.array_equal(b.mask()[2], orc.voxelise(CELL, cells[2]["spheres"]))
+    g0 = inputs.random_populations((4,) + CELL, 1e-3, seed=2)
+    b.set_state(g0)
+    b.step(5)
+    g = b.get_state()
+    for i, c in enumerate(cells):
+        o = _oracle(orc, c, collision=collision)
+        o.set_state(g0[:, i])
+        o.step(5)
+        fluid = o.mask == 0
+        err = np.max(np.abs(g[:, i][:, fluid] - o.g[:, fluid])) / np.max(np.abs(o.g[:, fluid]))
+        assert err < 1e-12, (i, err)
+    b.close()
+
+
+def test_batch_run_to_residual_per_cell(orc):
+    """Device-side convergence: every cell stops at its own check, with the
+    oracle's step count and permeability (FP64); the frozen cells keep their
+    final state while the others continue."""
+    cells = _cells(3, seed=3, drho_scale=1e-5)
+    for c in cells:
+        c["delta_rho"] = abs(c["delta_rho"]) + 1e-6
+    b = lbm.Batch(CELL, cells, wall="cli", storage="fp64", check_interval=50)
+    st, steps, res = b.run_to_residual(1e-9, 100000)
+    assert st == "converged"
+    r = b.results()
+    g = b.get_state()
+    assert len(set(r["steps"].tolist())) > 1  # cells stopped at different checks
+    for i, c in enumerate(cells):
+        o = _oracle(orc, c)
+        o.init()
+        so, no, _ = o.run_to_residual(1e-9, 100000, interval=50)
+        assert so == "converged" and r["status"][i] == "converged"
+        assert r["steps"][i] == no
+        assert abs(r["K_D"][i] / o.permeability() - 1) < 1e-10
+        fluid = o.mask == 0
+        err = np.max(np.abs(g[:, i][:, fluid] - o.g[:, fluid])) / np.max(np.abs(o.g[:, fluid]))
+        assert err < 1e-10
+    b.close()
+
+
+def test_batch_shapes_give_identical_bits():
+    """The launch shape chosen by the autotuner changes scheduling only."""
+    shape = (16, 10, 14)
+    cells = [dict(spheres=inputs.random_spheres(shape, 2, (1.5, 3.0), seed=40 + i),
+                  tau=0.6 + 0.2 * i, magic=0.2, delta_rho=1e-3 * (i + 1)) for i in range(3)]
+    u0 = inputs.random_velocity((3 * 16, 10, 14), 1e-2, seed=5)
+    outs = []
+    for by, zp in [(1, 1), (4, 2), (2, 4)]:
+        b = lbm.Batch(shape, cells, wall="cli", storage="fp32")
+        b.set_shape(by, zp)
+        b.init_equilibrium(u0=u0)
+        b.step(20)
+        outs.append(b.get_state())
+        b.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_batch_autotune_and_unstable_cell():
+    """The autotuner returns an admissible shape and resets to rest; an
+    unstable cell is flagged while the others converge."""
+    cells = _cells(3, seed=6, drho_scale=1e-5)
+    for c in cells:
+        c["delta_rho"] = abs(c["delta_rho"]) + 1e-6
+    cells[1].update(tau=0.5001, magic=0.25, delta_rho=0.5)
+    b = lbm.Batch((16, 10, 14), [dict(c, spheres=inputs.random_spheres((16, 10, 14), 2, (1.5, 3.0), seed=60 + i))
+                                 for i, c in enumerate(cells)], wall="cli", storage="fp32",
+                  check_interval=20)
+    by, zp, ms = b.autotune(steps=5)
+    assert by >= 1 and 16 % zp == 0 and ms > 0
+    assert np.all(b.get_state() == 0)
+    st, _, _ = b.run_to_residual(1e-7, 60000)
+    r = b.results()
+    assert st == "unstable"
+    assert r["status"][1] == "unstable"
+    assert r["status"][0] == "converged" and r["status"][2] == "converged"
+    b.close()
