@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
 
-SOURCES = ["lbm.hip", "geometry.cpp"]
+SOURCES = ["lbm.hip", "geometry.cpp", "nn.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIPCC_FLAGS = [

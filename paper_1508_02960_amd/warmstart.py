@@ -1,0 +1,369 @@
+"""Learned warm start for the lattice Boltzmann iteration.
+
+A 3-D U-Net with periodic padding maps the fluid indicator of a periodic
+sphere pack to the steady Stokes velocity, in the units t = u nu / G / scale
+(G = |grad P| = delta_rho / (3 nx)): Stokes flow is linear in the forcing, so
+t depends on the geometry only and one network serves every pressure drop
+and viscosity.  A run then starts from the equilibrium of the predicted
+velocity instead of rest; the plain iteration to the residual tolerance still
+decides the result, so the prediction only changes how many steps it takes.
+
+Every layer runs in the library's kernels (include/lbm_nn.h): BF16
+convolutions on matrix cores with FP32 accumulation, FP32 master weights
+updated by Adam.  PyTorch only provides device memory and the stream.
+
+Architecture (widths w0..w3, default 32, 64, 128, 256): one 3x3x3 conv + ReLU
+per level on the way down (2x2x2 average pooling between levels), and on the
+way up nearest upsampling, concatenation with the skip, conv + ReLU; a linear
+head conv gives 8 channels of which the first 3 are the velocity.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import inputs, lbm, observables
+
+IN_CH = 8     # channel 0: fluid indicator, 1..7: zeros (conv inputs need multiples of 8)
+OUT_CH = 8    # channels 0..2: velocity, 3..7: unused (kept at zero by the loss)
+
+
+def _nn():
+    lib = lbm.library()
+    if getattr(lib, "_nn_ready", False):
+        return lib
+    vp, i32, i64, f32, f64, sz = (C.c_void_p, C.c_int, C.c_longlong, C.c_float, C.c_double,
+                                  C.c_size_t)
+    sig = {
+        "nn_conv3d_forward": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
+        "nn_conv3d_flip_weights": [vp, vp, i32, i32, vp],
+        "nn_conv3d_backward_data": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
+        "nn_conv3d_backward_weight_workspace": [i32, i32, i32, i32, i32, i32, C.POINTER(sz),
+                                                C.POINTER(i32)],
+        "nn_conv3d_backward_weight": [vp, vp, vp, vp, sz, i32, i32, i32, i32, i32, i32, vp],
+        "nn_bias_grad": [vp, vp, i64, i32, vp],
+        "nn_activation_forward": [vp, vp, i64, i32, vp],
+        "nn_relu_backward": [vp, vp, vp, i64, vp],
+        "nn_cast_bf16": [vp, vp, i64, vp],
+        "nn_pool2_forward": [vp, vp, i32, i32, i32, i32, i32, vp],
+        "nn_pool2_backward": [vp, vp, i32, i32, i32, i32, i32, vp],
+        "nn_upsample2_forward": [vp, vp, i32, i32, i32, i32, i32, vp],
+        "nn_upsample2_backward": [vp, vp, i32, i32, i32, i32, i32, vp],
+        "nn_concat_channels": [vp, vp, vp, i64, i32, i32, vp],
+        "nn_split_channels": [vp, vp, vp, i64, i32, i32, vp],
+        "nn_add": [vp, vp, i64, vp],
+        "nn_masked_mse": [vp, vp, vp, vp, vp, i32, i64, i32, i32, f64, vp],
+        "nn_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib._nn_ready = True
+    return lib
+
+
+NN_EXPORTS = (
+    "nn_conv3d_forward", "nn_conv3d_flip_weights", "nn_conv3d_backward_data",
+    "nn_conv3d_backward_weight_workspace", "nn_conv3d_backward_weight", "nn_bias_grad",
+    "nn_activation_forward", "nn_relu_backward", "nn_cast_bf16", "nn_pool2_forward",
+    "nn_pool2_backward", "nn_upsample2_forward", "nn_upsample2_backward", "nn_concat_channels",
+    "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam",
+)
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _chk(st, what):
+    if st != 0:
+        raise lbm.LbmError(st, what)
+
+
+class _Ctx:
+    def __init__(self, device):
+        import torch
+
+        self.torch = torch
+        self.dev = torch.device(device if device is not None else "cuda")
+        self.stream = C.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def f32(self, *shape):
+        return self.torch.empty(shape, dtype=self.torch.float32, device=self.dev)
+
+    def bf(self, *shape):
+        return self.torch.empty(shape, dtype=self.torch.bfloat16, device=self.dev)
+
+    def zeros(self, *shape):
+        return self.torch.zeros(shape, dtype=self.torch.float32, device=self.dev)
+
+
+class Conv:
+    """3x3x3 periodic convolution ci -> co with bias; FP32 master weights,
+    BF16 copies for the kernels, Adam moments."""
+
+    def __init__(self, ctx: _Ctx, ci: int, co: int, rng: np.random.Generator):
+        self.ctx, self.ci, self.co = ctx, ci, co
+        std = np.sqrt(2.0 / (27 * ci))  # He initialisation for ReLU layers
+        w = (rng.standard_normal((co, 27, ci)) * std).astype(np.float32)
+        t = ctx.torch
+        self.w = t.from_numpy(w).to(ctx.dev)
+        self.b = ctx.zeros(co)
+        self.wb = ctx.bf(co, 27, ci)
+        self.wt = ctx.bf(ci, 27, co)
+        self.gw = ctx.zeros(co, 27, ci)
+        self.gb = ctx.zeros(co)
+        self.mw, self.vw = ctx.zeros(co, 27, ci), ctx.zeros(co, 27, ci)
+        self.mb, self.vb = ctx.zeros(co), ctx.zeros(co)
+        self.refresh()
+
+    def n_params(self) -> int:
+        return self.co * 27 * self.ci + self.co
+
+    def refresh(self):
+        lib = _nn()
+        _chk(lib.nn_cast_bf16(_p(self.w), _p(self.wb), self.w.numel(), self.ctx.stream), "cast")
+        _chk(lib.nn_conv3d_flip_weights(_p(self.wb), _p(self.wt), self.ci, self.co,
+                                        self.ctx.stream), "flip")
+
+    def forward(self, x_bf, shape):
+        n, d, h, w = shape
+        y = self.ctx.f32(n, d, h, w, self.co)
+        _chk(_nn().nn_conv3d_forward(_p(x_bf), _p(self.wb), _p(self.b), _p(y), n, d, h, w,
+                                     self.ci, self.co, self.ctx.stream), "conv forward")
+        return y
+
+    def backward(self, x_bf, dy32, shape, need_dx=True):
+        lib = _nn()
+        n, d, h, w = shape
+        m = n * d * h * w
+        dy = self.ctx.bf(n, d, h, w, self.co)
+        _chk(lib.nn_cast_bf16(_p(dy32), _p(dy), dy32.numel(), self.ctx.stream), "cast")
+        nbytes = C.c_size_t()
+        sp = C.c_int()
+        _chk(lib.nn_conv3d_backward_weight_workspace(n, d, h, w, self.ci, self.co,
+                                                     C.byref(nbytes), C.byref(sp)), "ws")
+        ws = self.ctx.torch.empty(int(nbytes.value), dtype=self.ctx.torch.uint8,
+                                  device=self.ctx.dev)
+        _chk(lib.nn_conv3d_backward_weight(_p(x_bf), _p(dy), _p(self.gw), _p(ws), nbytes.value,
+                                           n, d, h, w, self.ci, self.co, self.ctx.stream),
+             "conv backward weight")
+        _chk(lib.nn_bias_grad(_p(dy32), _p(self.gb), m, self.co, self.ctx.stream), "bias grad")
+        if not need_dx:
+            return None
+        dx = self.ctx.f32(n, d, h, w, self.ci)
+        _chk(lib.nn_conv3d_backward_data(_p(dy), _p(self.wt), _p(dx), n, d, h, w, self.ci,
+                                         self.co, self.ctx.stream), "conv backward data")
+        return dx
+
+    def adam(self, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+        lib = _nn()
+        _chk(lib.nn_adam(_p(self.w), _p(self.gw), _p(self.mw), _p(self.vw), _p(self.wb),
+                         self.w.numel(), lr, b1, b2, eps, step, self.ctx.stream), "adam")
+        _chk(lib.nn_adam(_p(self.b), _p(self.gb), _p(self.mb), _p(self.vb), None, self.co, lr,
+                         b1, b2, eps, step, self.ctx.stream), "adam")
+        _chk(lib.nn_conv3d_flip_weights(_p(self.wb), _p(self.wt), self.ci, self.co,
+                                        self.ctx.stream), "flip")
+
+
+class UNet:
+    def __init__(self, widths=(32, 64, 128, 256), seed: int = 0, device=None):
+        self.ctx = _Ctx(device)
+        rng = np.random.default_rng(seed)
+        w0, w1, w2, w3 = widths
+        self.widths = widths
+        self.enc = [Conv(self.ctx, IN_CH, w0, rng), Conv(self.ctx, w0, w1, rng),
+                    Conv(self.ctx, w1, w2, rng), Conv(self.ctx, w2, w3, rng)]
+        self.dec = [Conv(self.ctx, w3 + w2, w2, rng), Conv(self.ctx, w2 + w1, w1, rng),
+                    Conv(self.ctx, w1 + w0, w0, rng)]
+        self.head = Conv(self.ctx, w0, OUT_CH, rng)
+        # a linear head starts near zero output
+        self.head.w.mul_(0.1)
+        self.head.refresh()
+        self.step_count = 0
+
+    def layers(self):
+        return self.enc + self.dec + [self.head]
+
+    def n_params(self) -> int:
+        return sum(l.n_params() for l in self.layers())
+
+    # -------------------------------------------------------------- passes
+    def _act(self, z, relu=True):
+        a = self.ctx.bf(*z.shape)
+        _chk(_nn().nn_activation_forward(_p(z), _p(a), z.numel(), 1 if relu else 0,
+                                         self.ctx.stream), "activation")
+        return a
+
+    def forward(self, x_bf):
+        """x_bf: bf16 (n, d, h, w, 8), d, h, w divisible by 8.  Returns the
+        FP32 output (n, d, h, w, 8) and keeps what the backward pass needs."""
+        lib = _nn()
+        s = self.ctx.stream
+        n, d, h, w, _ = x_bf.shape
+        shapes = [(n, d >> l, h >> l, w >> l) for l in range(4)]
+        self.cache = dict(x=x_bf, shapes=shapes)
+        e, inp = [], x_bf
+        for lvl, conv in enumerate(self.enc):
+            if lvl > 0:
+                pn, pd, ph, pw = shapes[lvl - 1]
+                p = self.ctx.bf(*shapes[lvl], conv.ci)
+                _chk(lib.nn_pool2_forward(_p(inp), _p(p), pn, pd, ph, pw, conv.ci, s), "pool")
+                inp = p
+            self.cache[f"in{lvl}"] = inp
+            e.append(self._act(conv.forward(inp, shapes[lvl])))
+            inp = e[-1]
+        cur = e[3]
+        for j, conv in enumerate(self.dec):
+            lvl = 2 - j
+            ccur = self.widths[lvl + 1]
+            up = self.ctx.bf(*shapes[lvl], ccur)
+            qn, qd, qh, qw = shapes[lvl + 1]
+            _chk(lib.nn_upsample2_forward(_p(cur), _p(up), qn, qd, qh, qw, ccur, s), "upsample")
+            cat = self.ctx.bf(*shapes[lvl], conv.ci)
+            m = int(np.prod(shapes[lvl]))
+            _chk(lib.nn_concat_channels(_p(up), _p(e[lvl]), _p(cat), m, ccur, self.widths[lvl], s),
+                 "concat")
+            self.cache[f"cat{lvl}"] = cat
+            cur = self._act(conv.forward(cat, shapes[lvl]))
+            self.cache[f"d{lvl}"] = cur
+        self.cache["e"] = e
+        out = self.head.forward(cur, shapes[0])
+        return out
+
+    def backward(self, dout):
+        """Gradients of all weights for upstream gradient dout (n, d, h, w, 8)."""
+        lib = _nn()
+        s = self.ctx.stream
+        c = self.cache
+        shapes, e = c["shapes"], c["e"]
+        # head (linear)
+        g = self.head.backward(c["d0"], dout, shapes[0])
+        skip_grads = [None] * 3
+        for j, conv in enumerate(self.dec):
+            lvl = j  # backward goes 0, 1, 2 through decoder levels
+            conv = self.dec[2 - lvl]
+            act = c[f"d{lvl}"]
+            dz = self.ctx.f32(*act.shape)
+            _chk(lib.nn_relu_backward(_p(g), _p(act), _p(dz), act.numel(), s), "relu backward")
+            dcat = conv.backward(c[f"cat{lvl}"], dz, shapes[lvl])
+            ccur = self.widths[lvl + 1]
+            m = int(np.prod(shapes[lvl]))
+            dup = self.ctx.f32(*shapes[lvl], ccur)
+            dskip = self.ctx.f32(*shapes[lvl], self.widths[lvl])
+            _chk(lib.nn_split_channels(_p(dcat), _p(dup), _p(dskip), m, ccur, self.widths[lvl], s),
+                 "split")
+            skip_grads[lvl] = dskip
+            g = self.ctx.f32(*shapes[lvl + 1], ccur)
+            qn, qd, qh, qw = shapes[lvl + 1]
+            _chk(lib.nn_upsample2_backward(_p(dup), _p(g), qn, qd, qh, qw, ccur, s), "up backward")
+        # g: gradient of e[3]; down the encoder
+        for lvl in (3, 2, 1, 0):
+            conv = self.enc[lvl]
+            act = e[lvl]
+            if lvl < 3:
+                _chk(lib.nn_add(_p(g), _p(skip_grads[lvl]), g.numel(), s), "add")
+            dz = self.ctx.f32(*act.shape)
+            _chk(lib.nn_relu_backward(_p(g), _p(act), _p(dz), act.numel(), s), "relu backward")
+            dinp = conv.backward(c[f"in{lvl}"], dz, shapes[lvl], need_dx=lvl > 0)
+            if lvl > 0:
+                g = self.ctx.f32(*shapes[lvl - 1], conv.ci)
+                pn, pd, ph, pw = shapes[lvl - 1]
+                _chk(lib.nn_pool2_backward(_p(dinp), _p(g), pn, pd, ph, pw, conv.ci, s),
+                     "pool backward")
+
+    def adam_step(self, lr: float):
+        self.step_count += 1
+        for l in self.layers():
+            l.adam(lr, self.step_count)
+
+    # --------------------------------------------------------------- loss
+    def loss(self, out, target, weight, norm: float):
+        """Weighted MSE on the first 3 channels; returns (loss, grad)."""
+        lib = _nn()
+        m = out.numel() // OUT_CH
+        grad = self.ctx.f32(*out.shape)
+        nb = 1024
+        part = self.ctx.torch.empty(nb, dtype=self.ctx.torch.float64, device=self.ctx.dev)
+        _chk(lib.nn_masked_mse(_p(out), _p(target), _p(weight), _p(grad), _p(part), nb, m,
+                               OUT_CH, 3, float(norm), self.ctx.stream), "mse")
+        return float(part.sum().item()), grad
+
+
+# ------------------------------------------------------------------ data
+
+def network_input(ctx: _Ctx, fluid: np.ndarray):
+    """bf16 input (n, d, h, w, 8): channel 0 the fluid indicator."""
+    t = ctx.torch
+    x = np.zeros(fluid.shape + (IN_CH,), np.float32)
+    x[..., 0] = fluid
+    return t.from_numpy(x).to(ctx.dev).to(t.bfloat16)
+
+
+def percolates_x(fluid: np.ndarray) -> bool:
+    """True if fluid connects the plane x = 0 to x = nx - 1 through
+    face-neighbours, with y and z periodic."""
+    from scipy import ndimage
+
+    lab, n = ndimage.label(fluid)
+    if n == 0:
+        return False
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for ax in (0, 1):  # z and y faces wrap
+        a = np.take(lab, 0, axis=ax)
+        b = np.take(lab, -1, axis=ax)
+        both = (a > 0) & (b > 0)
+        for u, v in zip(a[both], b[both]):
+            ru, rv = find(u), find(v)
+            if ru != rv:
+                parent[ru] = rv
+    left = {find(v) for v in np.unique(lab[..., 0]) if v}
+    right = {find(v) for v in np.unique(lab[..., -1]) if v}
+    return bool(left & right)
+
+
+def random_packs(n_cells: int, edge: int, n_range, phi_range, seed: int):
+    """Seeded packs of overlapping spheres with a porosity near U(phi_range):
+    the radius follows the porosity of overlapping random spheres,
+    exp(-N (4/3) pi r^3 / V) = phi."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_cells):
+        ns = int(rng.integers(n_range[0], n_range[1] + 1))
+        phi = rng.uniform(*phi_range)
+        r = (-np.log(phi) * edge ** 3 * 3 / (4 * np.pi * ns)) ** (1 / 3)
+        r = min(r, edge / 2 - 1)
+        sp = np.hstack([rng.uniform(0, edge, size=(ns, 3)), np.full((ns, 1), r)])
+        out.append(sp)
+    return out
+
+
+def stokes_fields(edge: int, packs, tau: float = 0.8, tol: float = 1e-6, max_steps: int = 60000,
+                  device=None, log=None):
+    """Steady Stokes velocity of every pack (batch solver, FP32, TRT-CLI) in
+    the units u nu / G.  Returns (fluid masks, targets (n, d, h, w, 3), K_D)."""
+    drho = 1e-6
+    G = observables.pressure_gradient(drho, edge)
+    nu = observables.viscosity(tau)
+    cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=drho) for sp in packs]
+    b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
+    b.autotune(steps=5)
+    st, steps, _ = b.run_to_residual(tol, max_steps)
+    r = b.results()
+    _, u = b.macroscopic()  # (3, n, d, h, w)
+    fluid = (b.mask() == 0)
+    b.close()
+    if log:
+        log(f"[warmstart] stokes batch: {st}, max steps {steps}, statuses "
+            f"{ {s: r['status'].count(s) for s in set(r['status'])} }")
+    t = np.moveaxis(u, 0, -1) * (nu / G)
+    return fluid, t.astype(np.float32), r["K_D"], r["status"]

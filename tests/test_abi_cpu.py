@@ -12,10 +12,10 @@ from paper_1508_02960_amd import inputs, lbm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _header_functions():
-    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+def _header_functions(header="lbm.h", prefix="lbm_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_header_function():
@@ -25,6 +25,32 @@ def test_library_exports_every_header_function():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(lbm.EXPORTS)
+
+
+def test_library_exports_every_network_function():
+    from paper_1508_02960_amd import warmstart
+
+    lib = warmstart._nn()
+    names = _header_functions("lbm_nn.h", "nn_")
+    assert len(names) == 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(warmstart.NN_EXPORTS)
+
+
+def test_network_entry_points_validate_without_a_gpu():
+    from paper_1508_02960_amd import warmstart
+
+    lib = warmstart._nn()
+    nb, sp = C.c_size_t(), C.c_int()
+    # ci and co must be multiples of 8 for the weight gradient
+    assert lib.nn_conv3d_backward_weight_workspace(1, 8, 8, 8, 12, 16, C.byref(nb),
+                                                   C.byref(sp)) == 1
+    assert lib.nn_conv3d_backward_weight_workspace(1, 8, 8, 8, 16, 16, C.byref(nb),
+                                                   C.byref(sp)) == 0
+    assert nb.value == sp.value * 16 * 27 * 16 * 4 and 1 <= sp.value <= 256
+    assert lib.nn_conv3d_forward(None, None, None, None, 1, 4, 4, 4, 8, 8, None) == 1
+    assert lib.nn_pool2_forward(C.c_void_p(16), C.c_void_p(16), 1, 3, 4, 4, 8, None) == 1
 
 
 def _create(shape=(8, 9, 10), **kw):

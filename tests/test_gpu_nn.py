@@ -1,0 +1,253 @@
+"""Warm-start network kernels (BF16 MFMA convolutions and the layers around
+them) against the FP64 reference of oracle/nn_reference.py.
+
+Inputs are BF16 values, so products are exact in FP32 and the kernels differ
+from the FP64 reference only by FP32 accumulation: 1e-5 relative.  The whole
+network's gradients are compared with a CPU twin that rounds to BF16 at the
+same points (activations, upstream gradients): 2e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import nn_reference as R
+from paper_1508_02960_amd import warmstart as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return W._Ctx("cuda")
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def _bf_dev(ctx, a):
+    t = ctx.torch
+    return t.from_numpy(np.ascontiguousarray(a, np.float32)).to(ctx.dev).to(t.bfloat16)
+
+
+def _f_dev(ctx, a):
+    t = ctx.torch
+    return t.from_numpy(np.ascontiguousarray(a, np.float32)).to(ctx.dev)
+
+
+def _host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+SHAPES = [((2, 6, 4, 8), 8, 8), ((1, 4, 6, 4), 16, 24), ((1, 4, 4, 4), 32, 80),
+          ((1, 8, 8, 8), 8, 16)]
+
+
+@pytest.mark.parametrize("shape,ci,co", SHAPES)
+def test_conv_forward_backward_match_reference(ctx, shape, ci, co):
+    rng = np.random.default_rng(ci * 7 + co)
+    x = R.bf16(rng.standard_normal(shape + (ci,)))
+    w = R.bf16(rng.standard_normal((co, 27, ci)) * 0.2)
+    b = rng.standard_normal(co).astype(np.float32).astype(np.float64)
+    dy = R.bf16(rng.standard_normal(shape + (co,)))
+    lib = W._nn()
+    n, d, h, wd = shape
+    xd, wb, bd = _bf_dev(ctx, x), _bf_dev(ctx, w), _f_dev(ctx, b)
+    y = ctx.f32(n, d, h, wd, co)
+    assert lib.nn_conv3d_forward(W._p(xd), W._p(wb), W._p(bd), W._p(y), n, d, h, wd, ci, co,
+                                 ctx.stream) == 0
+    assert rel(_host(y), R.conv3d(x, w, b)) < 1e-5
+    dx_ref, dw_ref, db_ref = R.conv3d_backward(x, w, dy)
+    if co % 8 == 0:
+        wt = ctx.bf(ci, 27, co)
+        assert lib.nn_conv3d_flip_weights(W._p(wb), W._p(wt), ci, co, ctx.stream) == 0
+        dx = ctx.f32(n, d, h, wd, ci)
+        assert lib.nn_conv3d_backward_data(W._p(_bf_dev(ctx, dy)), W._p(wt), W._p(dx), n, d, h,
+                                           wd, ci, co, ctx.stream) == 0
+        assert rel(_host(dx), dx_ref) < 1e-5
+        import ctypes as C
+        nb = C.c_size_t()
+        sp = C.c_int()
+        assert lib.nn_conv3d_backward_weight_workspace(n, d, h, wd, ci, co, C.byref(nb),
+                                                       C.byref(sp)) == 0
+        ws = ctx.torch.empty(nb.value, dtype=ctx.torch.uint8, device=ctx.dev)
+        dw = ctx.f32(co, 27, ci)
+        assert lib.nn_conv3d_backward_weight(W._p(xd), W._p(_bf_dev(ctx, dy)), W._p(dw), W._p(ws),
+                                             nb.value, n, d, h, wd, ci, co, ctx.stream) == 0
+        assert rel(_host(dw), dw_ref) < 1e-5
+        db = ctx.f32(co)
+        assert lib.nn_bias_grad(W._p(_f_dev(ctx, dy)), W._p(db), n * d * h * wd, co,
+                                ctx.stream) == 0
+        assert rel(_host(db), db_ref) < 1e-5
+
+
+def test_pool_up_concat_split_relu(ctx):
+    rng = np.random.default_rng(3)
+    lib = W._nn()
+    s = ctx.stream
+    x = R.bf16(rng.standard_normal((2, 4, 6, 8, 8)))
+    y = ctx.bf(2, 2, 3, 4, 8)
+    assert lib.nn_pool2_forward(W._p(_bf_dev(ctx, x)), W._p(y), 2, 4, 6, 8, 8, s) == 0
+    assert rel(_host(y), R.bf16(R.pool2(x))) < 1e-6
+    dy = rng.standard_normal((2, 2, 3, 4, 8))
+    dx = ctx.f32(2, 4, 6, 8, 8)
+    assert lib.nn_pool2_backward(W._p(_f_dev(ctx, dy)), W._p(dx), 2, 4, 6, 8, 8, s) == 0
+    assert rel(_host(dx), R.pool2_backward(dy)) < 1e-6
+    xc = R.bf16(rng.standard_normal((1, 2, 3, 2, 8)))
+    yf = ctx.bf(1, 4, 6, 4, 8)
+    assert lib.nn_upsample2_forward(W._p(_bf_dev(ctx, xc)), W._p(yf), 1, 2, 3, 2, 8, s) == 0
+    assert np.array_equal(_host(yf), R.up2(xc))
+    dyf = rng.standard_normal((1, 4, 6, 4, 8))
+    dxc = ctx.f32(1, 2, 3, 2, 8)
+    assert lib.nn_upsample2_backward(W._p(_f_dev(ctx, dyf)), W._p(dxc), 1, 2, 3, 2, 8, s) == 0
+    assert rel(_host(dxc), R.up2_backward(dyf)) < 1e-6
+    a = R.bf16(rng.standard_normal((5, 8)))
+    b = R.bf16(rng.standard_normal((5, 16)))
+    cat = ctx.bf(5, 24)
+    assert lib.nn_concat_channels(W._p(_bf_dev(ctx, a)), W._p(_bf_dev(ctx, b)), W._p(cat), 5, 8,
+                                  16, s) == 0
+    assert np.array_equal(_host(cat), np.concatenate([a, b], axis=1))
+    g = rng.standard_normal((5, 24))
+    ga, gb = ctx.f32(5, 8), ctx.f32(5, 16)
+    assert lib.nn_split_channels(W._p(_f_dev(ctx, g)), W._p(ga), W._p(gb), 5, 8, 16, s) == 0
+    assert rel(_host(ga), g[:, :8]) < 1e-7 and rel(_host(gb), g[:, 8:]) < 1e-7
+    z = rng.standard_normal(1000)
+    act = ctx.bf(1000)
+    assert lib.nn_activation_forward(W._p(_f_dev(ctx, z)), W._p(act), 1000, 1, s) == 0
+    assert np.array_equal(_host(act), R.bf16(np.maximum(z, 0)))
+    da = rng.standard_normal(1000)
+    dz = ctx.f32(1000)
+    assert lib.nn_relu_backward(W._p(_f_dev(ctx, da)), W._p(act), W._p(dz), 1000, s) == 0
+    assert np.allclose(_host(dz), np.where(R.bf16(np.maximum(z, 0)) > 0,
+                                           da.astype(np.float32), 0))
+
+
+def test_mse_and_adam(ctx):
+    rng = np.random.default_rng(4)
+    lib = W._nn()
+    m = 300
+    pred = rng.standard_normal((m, 8)).astype(np.float32)
+    tgt = rng.standard_normal((m, 3)).astype(np.float32)
+    wgt = (rng.uniform(size=m) > 0.3).astype(np.float32)
+    norm = 3.0 * wgt.sum()
+    grad = ctx.f32(m, 8)
+    part = ctx.torch.empty(64, dtype=ctx.torch.float64, device=ctx.dev)
+    assert lib.nn_masked_mse(W._p(_f_dev(ctx, pred)), W._p(_f_dev(ctx, tgt)),
+                             W._p(_f_dev(ctx, wgt)), W._p(grad), W._p(part), 64, m, 8, 3, norm,
+                             ctx.stream) == 0
+    d = pred[:, :3].astype(np.float64) - tgt
+    loss = float(np.sum(d ** 2 * wgt[:, None]) / norm)
+    assert abs(float(part.sum().item()) - loss) < 1e-6 * loss
+    g_ref = np.zeros((m, 8))
+    g_ref[:, :3] = 2 * d * wgt[:, None] / norm
+    assert rel(_host(grad), g_ref) < 1e-6
+    # Adam, two steps against the textbook update
+    w = rng.standard_normal(50)
+    gs = [rng.standard_normal(50), rng.standard_normal(50)]
+    wd, m1, m2 = _f_dev(ctx, w), ctx.zeros(50), ctx.zeros(50)
+    ref, a, b = w.copy(), np.zeros(50), np.zeros(50)
+    for t, g in enumerate(gs, start=1):
+        assert lib.nn_adam(W._p(wd), W._p(_f_dev(ctx, g)), W._p(m1), W._p(m2), None, 50, 1e-2,
+                           0.9, 0.999, 1e-8, t, ctx.stream) == 0
+        a = 0.9 * a + 0.1 * g
+        b = 0.999 * b + 0.001 * g * g
+        ref = ref - 1e-2 * (a / (1 - 0.9 ** t)) / (np.sqrt(b / (1 - 0.999 ** t)) + 1e-8)
+    assert rel(_host(wd), ref) < 1e-5
+
+
+def _cpu_unet(net, x, target, weight, norm):
+    """CPU twin of UNet forward/backward in FP64 with BF16 rounding where the
+    GPU stores BF16 (weights, activations, concatenations, gradients fed to
+    the convolution backward)."""
+    def wts(conv):
+        return (R.bf16(conv.w.cpu().numpy().astype(np.float64)),
+                conv.b.cpu().numpy().astype(np.float64))
+
+    e, ins = [], []
+    inp = x
+    for lvl, conv in enumerate(net.enc):
+        if lvl > 0:
+            inp = R.bf16(R.pool2(inp))
+        ins.append(inp)
+        w, b = wts(conv)
+        e.append(R.bf16(np.maximum(R.conv3d(inp, w, b), 0)))
+        inp = e[-1]
+    cur, cats, ds = e[3], {}, {}
+    for j, conv in enumerate(net.dec):
+        lvl = 2 - j
+        cat = np.concatenate([R.up2(cur), e[lvl]], axis=-1)
+        cats[lvl] = cat
+        w, b = wts(conv)
+        cur = R.bf16(np.maximum(R.conv3d(cat, w, b), 0))
+        ds[lvl] = cur
+    wh, bh = wts(net.head)
+    out = R.conv3d(ds[0], wh, bh)
+    d = out[..., :3] - target
+    loss = np.sum(d ** 2 * weight[..., None]) / norm
+    dout = np.zeros_like(out)
+    dout[..., :3] = 2 * d * weight[..., None] / norm
+    grads = {}
+    g, grads["head"], _ = R.conv3d_backward(ds[0], wh, R.bf16(dout))
+    skip = {}
+    for lvl in (0, 1, 2):
+        conv = net.dec[2 - lvl]
+        dz = np.where(ds[lvl] > 0, g, 0)
+        w, _ = wts(conv)
+        dcat, grads[f"dec{lvl}"], _ = R.conv3d_backward(cats[lvl], w, R.bf16(dz))
+        cc = net.widths[lvl + 1]
+        skip[lvl] = dcat[..., cc:]
+        g = R.up2_backward(dcat[..., :cc])
+    for lvl in (3, 2, 1, 0):
+        if lvl < 3:
+            g = g + skip[lvl]
+        dz = np.where(e[lvl] > 0, g, 0)
+        w, _ = wts(net.enc[lvl])
+        dinp, grads[f"enc{lvl}"], _ = R.conv3d_backward(ins[lvl], w, R.bf16(dz))
+        if lvl > 0:
+            g = R.pool2_backward(dinp)
+    return out, loss, grads
+
+
+def test_unet_gradients_match_cpu_twin(ctx):
+    net = W.UNet(widths=(8, 8, 16, 16), seed=7, device="cuda")
+    rng = np.random.default_rng(8)
+    shape = (1, 16, 16, 16)
+    fluid = (rng.uniform(size=shape) > 0.3).astype(np.float32)
+    x_np = np.zeros(shape + (8,))
+    x_np[..., 0] = fluid
+    target = rng.standard_normal(shape + (3,)).astype(np.float32)
+    norm = 3.0 * fluid.sum()
+    out = net.forward(W.network_input(net.ctx, fluid))
+    loss, dout = net.loss(out, _f_dev(ctx, target), _f_dev(ctx, fluid), norm)
+    net.backward(dout)
+    out_ref, loss_ref, g_ref = _cpu_unet(net, x_np, target.astype(np.float64),
+                                         fluid.astype(np.float64), norm)
+    assert rel(_host(out), out_ref) < 2e-3
+    assert abs(loss / loss_ref - 1) < 2e-3
+    assert rel(_host(net.head.gw), g_ref["head"]) < 2e-3
+    for lvl in range(3):
+        assert rel(_host(net.dec[2 - lvl].gw), g_ref[f"dec{lvl}"]) < 2e-3, lvl
+    for lvl in range(4):
+        assert rel(_host(net.enc[lvl].gw), g_ref[f"enc{lvl}"]) < 2e-3, lvl
+
+
+def test_unet_training_reduces_loss(ctx):
+    """A few Adam steps on a fixed target lower the loss."""
+    net = W.UNet(widths=(8, 16, 16, 32), seed=9, device="cuda")
+    rng = np.random.default_rng(10)
+    shape = (2, 16, 16, 16)
+    fluid = (rng.uniform(size=shape) > 0.3).astype(np.float32)
+    target = (np.sin(np.arange(16) / 3.0)[None, None, None, :, None]
+              * fluid[..., None] * np.ones(3)).astype(np.float32)
+    x = W.network_input(net.ctx, fluid)
+    t, wgt = _f_dev(ctx, target), _f_dev(ctx, fluid)
+    losses = []
+    for _ in range(30):
+        out = net.forward(x)
+        loss, g = net.loss(out, t, wgt, 3.0 * fluid.sum())
+        net.backward(g)
+        net.adam_step(3e-3)
+        losses.append(loss)
+    assert losses[-1] < 0.5 * losses[0], losses
