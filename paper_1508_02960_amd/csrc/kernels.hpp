@@ -368,7 +368,7 @@ __device__ __host__ constexpr int wclass(int k) { return k == 0 ? 0 : (k < 7 ? 1
 // wall rule, pressure jump, collision, store.  Returns the pre-collision
 // moments (which the collision conserves) and max_k |g*_k| / w_k of the
 // stored result, for the optional reduction.
-template <typename S, int COLL, int WALL>
+template <typename S, int COLL, int WALL, bool NT = false>
 __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __restrict__ dst,
                                             const StepParams& p, int x, int y, int z, int c,
                                             uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
@@ -473,6 +473,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
     for (int k = 0; k < kQ; ++k)
       dst[k * st + c] = St::from_float_sr(g[k] * enc[wclass(k)],
                                           (base + (uint32_t)k * 0x9e3779b9u) * 0x85ebca6bu);
+  } else if constexpr (NT) {
+    // streaming stores: the new state is not read again within this step
+#pragma unroll
+    for (int k = 0; k < kQ; ++k)
+      __builtin_nontemporal_store(St::from_float(g[k] * enc[wclass(k)]), &dst[k * st + c]);
   } else {
 #pragma unroll
     for (int k = 0; k < kQ; ++k) dst[k * st + c] = St::from_float(g[k] * enc[wclass(k)]);
@@ -487,8 +492,9 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
 // full x rows (bx >= nx, up to 512) so that the +-1 shifted row reads of a
 // row stay inside one workgroup.  With RED the block also writes FP64
 // partial sums of the state it produced (u, drho, max |u|^2, non-finite
-// count) to partials[block].
-template <typename S, int COLL, int WALL, bool RED>
+// count) to partials[block].  NT selects non-temporal stores (FP32 and
+// FP64 storage only).
+template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
                                                    S* __restrict__ dst,
                                                    const uint32_t* __restrict__ flags,
@@ -505,13 +511,13 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
     const uint32_t fl = flags[c];
     if (fl & kSolid) return;
     C mom[5];
-    update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
+    update_node<S, COLL, WALL, NT>(src, dst, p, x, y, z, c, fl, mom);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t fl = inside ? flags[c] : kSolid;
     if (!(fl & kSolid)) {
       C mom[5];
-      update_node<S, COLL, WALL>(src, dst, p, x, y, z, c, fl, mom);
+      update_node<S, COLL, WALL, NT>(src, dst, p, x, y, z, c, fl, mom);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
       v[0] = ux;
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
 // (converged or stopped) cells.  Block ids of cell b are contiguous, so the
 // partial sums of a cell form one segment.
 
-template <typename S, int COLL, int WALL, bool RED>
+template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(1024) void batch_step_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const uint32_t* __restrict__ flags,
     const StepParams* __restrict__ cells, const int* __restrict__ active, int nz_cell,
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(
     const uint32_t fl = inside ? f[c] : kSolid;
     if (fl & kSolid) continue;
     C mom[5];
-    update_node<S, COLL, WALL>(s, d, p, x, y, z, c, fl, mom);
+    update_node<S, COLL, WALL, NT>(s, d, p, x, y, z, c, fl, mom);
     if constexpr (RED) {
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;

@@ -67,3 +67,15 @@ def batch_cell_draws(seed: int, edge: int = 64):
         tau = rng.uniform(0.55, 1.0)
         log_re = rng.uniform(-3.0, np.log10(300.0))
         yield dict(diameter=d, centre=c, tau=tau, re_p=10.0 ** log_re)
+
+
+def pack_draws(seed: int, edge: int, n_range, phi_range):
+    """Endless seeded draws for random packs of overlapping spheres of one
+    common radius: sphere count U{n_range}, centres U[0, edge)^3, target
+    porosity U[phi_range].  The caller fits the radius to the porosity."""
+    rng = np.random.default_rng(seed)
+    while True:
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        c = rng.uniform(0.0, float(edge), size=(n, 3))
+        phi = rng.uniform(phi_range[0], phi_range[1])
+        yield dict(centres=c, porosity=phi)

@@ -15,7 +15,9 @@ updated by Adam.  PyTorch only provides device memory and the stream.
 Architecture (widths w0..w3, default 32, 64, 128, 256): one 3x3x3 conv + ReLU
 per level on the way down (2x2x2 average pooling between levels), and on the
 way up nearest upsampling, concatenation with the skip, conv + ReLU; a linear
-head conv gives 8 channels of which the first 3 are the velocity.
+head conv gives 8 channels: the velocity (0..2) and the periodic part of the
+density (3), both in the target units of fields_to_targets.  The forcing
+is not an input: in the Stokes regime it only scales the output.
 """
 from __future__ import annotations
 
@@ -26,7 +28,7 @@ import numpy as np
 from . import inputs, lbm, observables
 
 IN_CH = 8     # channel 0: fluid indicator, 1..7: zeros (conv inputs need multiples of 8)
-OUT_CH = 8    # channels 0..2: velocity, 3..7: unused (kept at zero by the loss)
+OUT_CH = 8    # channels 0..2: velocity, 3: pressure fluctuation, 4..7: unused
 
 
 def _nn():
@@ -183,6 +185,7 @@ class UNet:
         self.head.w.mul_(0.1)
         self.head.refresh()
         self.step_count = 0
+        self.scale = 1.0  # target units per output unit
 
     def layers(self):
         return self.enc + self.dec + [self.head]
@@ -280,26 +283,60 @@ class UNet:
             l.adam(lr, self.step_count)
 
     # --------------------------------------------------------------- loss
-    def loss(self, out, target, weight, norm: float):
-        """Weighted MSE on the first 3 channels; returns (loss, grad)."""
+    def loss(self, out, target, weight, norm: float, sync: bool = True):
+        """Weighted MSE of the first target.shape[-1] output channels against
+        target; returns (loss, grad), the loss as a device scalar when
+        sync is False."""
         lib = _nn()
         m = out.numel() // OUT_CH
+        used = int(target.shape[-1])
         grad = self.ctx.f32(*out.shape)
         nb = 1024
         part = self.ctx.torch.empty(nb, dtype=self.ctx.torch.float64, device=self.ctx.dev)
         _chk(lib.nn_masked_mse(_p(out), _p(target), _p(weight), _p(grad), _p(part), nb, m,
-                               OUT_CH, 3, float(norm), self.ctx.stream), "mse")
-        return float(part.sum().item()), grad
+                               OUT_CH, used, float(norm), self.ctx.stream), "mse")
+        total = part.sum()
+        return (float(total.item()) if sync else total), grad
+
+    # ------------------------------------------------------ use and storage
+    def predict(self, fluid: np.ndarray, used: int = 4) -> np.ndarray:
+        """Targets (nz, ny, nx, used) for one fluid mask (edges multiples of
+        8), in target units (the output times self.scale)."""
+        out = self.forward(network_input(self.ctx, fluid[None].astype(np.uint8)))
+        return out[0, ..., :used].float().cpu().numpy() * self.scale
+
+    def save(self, path: str) -> None:
+        arrays = {"widths": np.array(self.widths), "scale": np.array(self.scale),
+                  "step_count": np.array(self.step_count)}
+        for i, l in enumerate(self.layers()):
+            arrays[f"w{i}"] = l.w.cpu().numpy()
+            arrays[f"b{i}"] = l.b.cpu().numpy()
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load(cls, path: str, device=None) -> "UNet":
+        z = np.load(path)
+        net = cls(widths=tuple(int(v) for v in z["widths"]), device=device)
+        net.scale = float(z["scale"])
+        net.step_count = int(z["step_count"])
+        for i, l in enumerate(net.layers()):
+            l.w.copy_(net.ctx.torch.from_numpy(z[f"w{i}"]))
+            l.b.copy_(net.ctx.torch.from_numpy(z[f"b{i}"]))
+            l.refresh()
+        return net
 
 
 # ------------------------------------------------------------------ data
 
-def network_input(ctx: _Ctx, fluid: np.ndarray):
-    """bf16 input (n, d, h, w, 8): channel 0 the fluid indicator."""
+def network_input(ctx: _Ctx, fluid):
+    """bf16 input (n, d, h, w, 8) with the fluid indicator in channel 0, from
+    a host array or a device tensor of shape (n, d, h, w)."""
     t = ctx.torch
-    x = np.zeros(fluid.shape + (IN_CH,), np.float32)
-    x[..., 0] = fluid
-    return t.from_numpy(x).to(ctx.dev).to(t.bfloat16)
+    f = fluid if isinstance(fluid, t.Tensor) else t.from_numpy(np.ascontiguousarray(fluid))
+    f = f.to(ctx.dev)
+    x = t.zeros(tuple(f.shape) + (IN_CH,), dtype=t.bfloat16, device=ctx.dev)
+    x[..., 0] = f.to(t.bfloat16)
+    return x
 
 
 def percolates_x(fluid: np.ndarray) -> bool:
@@ -331,39 +368,72 @@ def percolates_x(fluid: np.ndarray) -> bool:
     return bool(left & right)
 
 
-def random_packs(n_cells: int, edge: int, n_range, phi_range, seed: int):
-    """Seeded packs of overlapping spheres with a porosity near U(phi_range):
-    the radius follows the porosity of overlapping random spheres,
-    exp(-N (4/3) pi r^3 / V) = phi."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(n_cells):
-        ns = int(rng.integers(n_range[0], n_range[1] + 1))
-        phi = rng.uniform(*phi_range)
-        r = (-np.log(phi) * edge ** 3 * 3 / (4 * np.pi * ns)) ** (1 / 3)
-        r = min(r, edge / 2 - 1)
-        sp = np.hstack([rng.uniform(0, edge, size=(ns, 3)), np.full((ns, 1), r)])
-        out.append(sp)
+# ------------------------------------------------------- target units
+# Stokes flow is linear in the forcing, so the steady fields divided by the
+# pressure gradient depend on the geometry alone.  With G = delta_rho / (3 nx)
+# and the density written as the linear part -(delta_rho / nx)(x - (nx-1)/2)
+# plus a periodic fluctuation rho', the targets are
+#   t_u = u nu / G                      (length^2)
+#   t_p = rho' nx / delta_rho           (length)
+# and every target is further divided by the network's output scale.
+
+def fields_to_targets(drho, u, delta_rho: float, tau: float, fluid):
+    """(nz, ny, nx) density deviation and (3, nz, ny, nx) velocity of a
+    steady run -> (nz, ny, nx, 4) targets; rho' has zero mean over fluid."""
+    nz, ny, nx = drho.shape
+    G = observables.pressure_gradient(delta_rho, nx)
+    nu = observables.viscosity(tau)
+    x = np.arange(nx) - (nx - 1) / 2.0
+    tp = drho * (nx / delta_rho) + x[None, None, :]
+    tp = np.where(fluid, tp - tp[fluid].mean(), 0.0)
+    out = np.empty((nz, ny, nx, 4), np.float32)
+    out[..., :3] = np.moveaxis(u, 0, -1) * (nu / G)
+    out[..., 3] = tp
     return out
 
 
-def stokes_fields(edge: int, packs, tau: float = 0.8, tol: float = 1e-6, max_steps: int = 60000,
-                  device=None, log=None):
-    """Steady Stokes velocity of every pack (batch solver, FP32, TRT-CLI) in
-    the units u nu / G.  Returns (fluid masks, targets (n, d, h, w, 3), K_D)."""
-    drho = 1e-6
-    G = observables.pressure_gradient(drho, edge)
+def targets_to_fields(t, delta_rho: float, tau: float, fluid):
+    """Inverse of fields_to_targets: (drho, u) for lbm_init_equilibrium,
+    zero on solid nodes."""
+    nz, ny, nx, _ = t.shape
+    G = observables.pressure_gradient(delta_rho, nx)
     nu = observables.viscosity(tau)
-    cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=drho) for sp in packs]
-    b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
-    b.autotune(steps=5)
-    st, steps, _ = b.run_to_residual(tol, max_steps)
-    r = b.results()
-    _, u = b.macroscopic()  # (3, n, d, h, w)
-    fluid = (b.mask() == 0)
-    b.close()
-    if log:
-        log(f"[warmstart] stokes batch: {st}, max steps {steps}, statuses "
-            f"{ {s: r['status'].count(s) for s in set(r['status'])} }")
-    t = np.moveaxis(u, 0, -1) * (nu / G)
-    return fluid, t.astype(np.float32), r["K_D"], r["status"]
+    x = np.arange(nx) - (nx - 1) / 2.0
+    drho = (t[..., 3].astype(np.float64) - x[None, None, :]) * (delta_rho / nx)
+    u = np.moveaxis(t[..., :3].astype(np.float64), -1, 0) * (G / nu)
+    return np.where(fluid, drho, 0.0), np.where(fluid[None], u, 0.0)
+
+
+def linear_density(shape, delta_rho: float, fluid):
+    """The linear part of the steady density, -(delta_rho/nx)(x - (nx-1)/2),
+    on fluid nodes."""
+    nx = shape[-1]
+    x = np.arange(nx) - (nx - 1) / 2.0
+    return np.where(fluid, -(delta_rho / nx) * x, 0.0)
+
+
+_D3Q19_NEIGHBOURS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                     if 0 < abs(dz) + abs(dy) + abs(dx) <= 2]
+
+
+def wall_layer(fluid: np.ndarray) -> np.ndarray:
+    """Fluid nodes with at least one solid node among their 18 lattice
+    neighbours (periodic), over the last three axes."""
+    solid_nb = np.zeros(fluid.shape, bool)
+    for off in _D3Q19_NEIGHBOURS:
+        solid_nb |= ~np.roll(fluid, off, axis=(-3, -2, -1))
+    return fluid & solid_nb
+
+
+def warm_fields(t, delta_rho: float, tau: float, fluid, use_density: bool = False):
+    """Initial (drho, u) of a warm start from predicted targets t.  The
+    predicted velocity is used away from walls only: on the wall layer an
+    imposed velocity that differs from the wall-consistent one excites
+    slowly decaying period-2 oscillations of the bounce-back links, so the
+    wall layer starts at rest.  The density is the linear profile of the
+    pressure drop, plus the predicted fluctuation if use_density."""
+    drho, u = targets_to_fields(t, delta_rho, tau, fluid)
+    u = np.where(wall_layer(fluid)[None], 0.0, u)
+    if not use_density:
+        drho = linear_density(fluid.shape, delta_rho, fluid)
+    return drho, u

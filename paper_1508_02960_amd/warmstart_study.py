@@ -1,0 +1,364 @@
+"""Learned warm start: training fields from the batch solver, training of the
+U-Net on the GPU, and cold- versus warm-start runs to a residual.
+
+Training cells are periodic cubes of random overlapping spheres of one common
+radius (1-4 spheres per 64^3 cell, porosity U[0.35, 0.6]); the evaluation
+packs hold 8-27 spheres per 128^3 cell at the same porosities, so both sets
+share the radius range (about 20-40 lattice units).  Only packs whose pore
+space percolates in x are kept.  Every cell is solved in the Stokes regime
+by the batch solver (TRT, Lambda = 3/16, CLI walls, FP32); with Lambda fixed
+the steady TRT solution in the units of warmstart.fields_to_targets does not
+depend on tau, so the training fields use tau = 1 (fast relaxation) and the
+evaluation runs use tau = 0.8.
+
+Several starts are compared on the same evaluation batch, each run by the
+plain iteration to the residual tolerance: rest (g = 0), the linear density
+profile of the pressure drop with u = 0, the network's velocity (its wall
+layer at rest) with and without its density fluctuation, and the converged
+fields themselves (the bound of any start from an equilibrium).  The
+iteration decides the permeability in all of them.
+
+    python -m paper_1508_02960_amd.warmstart_study train --out unet.npz
+    python -m paper_1508_02960_amd.warmstart_study evaluate --weights unet.npz --out eval.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, lbm, observables
+from . import warmstart as W
+
+TRAIN_SPHERES = (1, 4)
+EVAL_SPHERES = (8, 27)
+POROSITY = (0.35, 0.6)
+
+
+def _log(msg: str) -> None:
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------- packs
+
+def fit_pack(draw, edge: int):
+    """Common radius that gives the drawn porosity on the lattice, and the
+    fluid mask: node p is solid iff its squared periodic distance to a
+    centre is below r^2, so the solid count is a quantile of those squared
+    distances (r^2 is placed midway between two of them)."""
+    ax = np.arange(edge, dtype=np.float64)
+    d2 = np.full((edge, edge, edge), np.inf)
+    for cx, cy, cz in draw["centres"]:
+        per = []
+        for v in (cz, cy, cx):
+            a = np.abs(ax - v)
+            per.append(np.minimum(a, edge - a) ** 2)
+        d2 = np.minimum(d2, per[0][:, None, None] + per[1][None, :, None] + per[2][None, None, :])
+    flat = np.sort(d2.ravel())
+    k = int(round((1.0 - draw["porosity"]) * flat.size))
+    k = min(max(k, 1), flat.size - 1)
+    r2 = 0.5 * (flat[k - 1] + flat[k])
+    r = float(np.sqrt(r2))
+    spheres = np.hstack([draw["centres"], np.full((len(draw["centres"]), 1), r)])
+    return spheres, d2 >= r2
+
+
+def draw_packs(n: int, edge: int, seed: int, n_range, phi_range=POROSITY):
+    """n percolating packs: list of (spheres, fluid mask)."""
+    out = []
+    for dr in inputs.pack_draws(seed, edge, n_range, phi_range):
+        if len(out) == n:
+            break
+        spheres, fluid = fit_pack(dr, edge)
+        if W.percolates_x(fluid):
+            out.append((spheres, fluid))
+    return out
+
+
+# ---------------------------------------------------------------- solving
+
+def solve_stokes(packs, edge: int, tau: float, delta_rho: float, tol: float, max_steps: int,
+                 device=None):
+    """Steady fields of every pack by one batch run; returns targets
+    (n, e, e, e, 4) float32, fluid masks (n, e, e, e) bool, results dict."""
+    cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
+    b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
+    try:
+        b.autotune(steps=5)
+        b.run_to_residual(tol, max_steps)
+        res = b.results()
+        drho, u = b.macroscopic()
+        fluid = b.mask() == 0
+    finally:
+        b.close()
+    t = np.stack([W.fields_to_targets(drho[i], u[:, i], delta_rho, tau, fluid[i])
+                  for i in range(len(packs))])
+    return t, fluid, res
+
+
+def training_set(n_cells: int, edge: int, seed: int, per_batch: int, tau: float,
+                 delta_rho: float, tol: float, max_steps: int, device=None, log=_log):
+    """Device tensors (fluid uint8 (n, e, e, e), targets float32 (n, e, e, e, 4))
+    of converged cells, from batches of per_batch cells with seeds seed, seed+1..."""
+    import torch
+
+    dev = torch.device(device if device is not None else "cuda")
+    fl, tg = [], []
+    b = 0
+    while sum(len(f) for f in fl) < n_cells:
+        t0 = time.perf_counter()
+        want = min(per_batch, n_cells - sum(len(f) for f in fl))
+        packs = draw_packs(want, edge, seed + b, TRAIN_SPHERES)
+        t, fluid, res = solve_stokes(packs, edge, tau, delta_rho, tol, max_steps, device)
+        ok = np.array([s == "converged" for s in res["status"]])
+        fl.append(torch.from_numpy(fluid[ok].astype(np.uint8)).to(dev))
+        tg.append(torch.from_numpy(t[ok]).to(dev))
+        log(f"[train-data] batch {b}: {ok.sum()}/{len(ok)} converged, steps max "
+            f"{int(res['steps'].max())}, K_D median {np.median(res['K_D']):.3g}, "
+            f"{time.perf_counter() - t0:.1f} s")
+        b += 1
+    return torch.cat(fl)[:n_cells], torch.cat(tg)[:n_cells]
+
+
+# --------------------------------------------------------------- training
+
+def rel_errors(net, fluid, targets, minibatch: int = 4):
+    """Relative L2 errors (velocity, density fluctuation) of the network on
+    the given cells, over fluid nodes; targets in network output units."""
+    torch = net.ctx.torch
+    num = torch.zeros(2, dtype=torch.float64, device=net.ctx.dev)
+    den = torch.zeros(2, dtype=torch.float64, device=net.ctx.dev)
+    for i in range(0, len(fluid), minibatch):
+        f = fluid[i:i + minibatch]
+        out = net.forward(W.network_input(net.ctx, f))[..., :4].double()
+        t = targets[i:i + minibatch].double()
+        w = f.double()[..., None]
+        e2 = (out - t) ** 2 * w
+        t2 = t ** 2 * w
+        num += torch.stack([e2[..., :3].sum(), e2[..., 3].sum()])
+        den += torch.stack([t2[..., :3].sum(), t2[..., 3].sum()])
+    r = (num / den).sqrt().cpu().numpy()
+    return float(r[0]), float(r[1])
+
+
+def train(net, fluid, targets, *, epochs: int, minibatch: int, lr: float, val_frac: float = 0.04,
+          time_limit: float = 1e30, seed: int = 0, log=_log, checkpoint=None):
+    """Adam on the weighted MSE over fluid nodes, cosine learning rate with
+    a short warm-up; the last val_frac of the cells are held out.  targets
+    are in target units; the network learns them divided by net.scale."""
+    torch = net.ctx.torch
+    n = len(fluid)
+    n_val = max(1, int(round(val_frac * n))) if n > 1 else 0
+    n_tr = n - n_val
+    w = fluid[:n_tr].bool()[..., None]
+    net.scale = float(torch.sqrt((targets[:n_tr, ..., :3] ** 2 * w).sum()
+                                 / (3 * w.sum())).item())
+    tn = targets / net.scale
+    rng = np.random.default_rng(seed)
+    steps_per_epoch = max(1, n_tr // minibatch)
+    total = epochs * steps_per_epoch
+    warm = min(100, total // 10 + 1)
+    t0 = time.perf_counter()
+    history = []
+    step = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n_tr)
+        acc = torch.zeros((), dtype=torch.float64, device=net.ctx.dev)
+        for j in range(steps_per_epoch):
+            idx = torch.from_numpy(perm[j * minibatch:(j + 1) * minibatch]).to(net.ctx.dev)
+            f = fluid[idx]
+            out = net.forward(W.network_input(net.ctx, f))
+            wt = f.float()
+            loss, g = net.loss(out, tn[idx], wt, 4.0 * float(wt.sum().item()), sync=False)
+            net.backward(g)
+            frac = step / max(total - 1, 1)
+            rate = lr * min(1.0, (step + 1) / warm) * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * frac)))
+            net.adam_step(rate)
+            acc += loss
+            step += 1
+        train_loss = float(acc.item()) / steps_per_epoch
+        ev = rel_errors(net, fluid[n_tr:], tn[n_tr:]) if n_val else (float("nan"),) * 2
+        el = time.perf_counter() - t0
+        history.append(dict(epoch=ep, loss=train_loss, val_rel_u=ev[0], val_rel_p=ev[1],
+                            seconds=el))
+        log(f"[train] epoch {ep}: loss {train_loss:.4g}, held-out relative error u {ev[0]:.4f} "
+            f"p {ev[1]:.4f}, {el:.0f} s")
+        if checkpoint:
+            net.save(checkpoint)
+        if el > time_limit:
+            log(f"[train] time limit reached after epoch {ep}")
+            break
+    return history
+
+
+# ------------------------------------------------------------- evaluation
+
+def _run(b, tol, max_steps, log, name):
+    """Run the batch from its current state to tol; per-cell results."""
+    t0 = time.perf_counter()
+    st, steps, _ = b.run_to_residual(tol, max_steps)
+    el = time.perf_counter() - t0
+    r = b.results()
+    out = dict(seconds=el, steps=r["steps"].tolist(), K_D=r["K_D"].tolist(), U=r["U"][:, 0].tolist(),
+               status=r["status"])
+    log(f"[eval] {name}: {el:.1f} s, steps median {np.median(r['steps']):.0f} "
+        f"max {r['steps'].max()}, statuses {dict((s, r['status'].count(s)) for s in set(r['status']))}")
+    return out
+
+
+def _trajectory(b, start, chunk, n_chunks):
+    """Per-cell U_x after each of n_chunks runs of chunk steps from start
+    (tolerance 0, so every cell runs the full chunk)."""
+    b.init_equilibrium(*start)
+    traj = []
+    for _ in range(n_chunks):
+        b.run_to_residual(0.0, chunk)
+        traj.append(b.results()["U"][:, 0].copy())
+    return np.array(traj)  # (n_chunks, n_cells)
+
+
+def evaluate(net, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
+             device=None, log=_log, chunk: int = 0, n_chunks: int = 0):
+    """Starts of the same packs, each run to tol by the plain iteration:
+    rest; linear density; the network's velocity (wall layer at rest) with
+    the linear density; the same plus the network's density fluctuation;
+    and, as the bound of any equilibrium-initialised warm start, the
+    converged fields of the rest run.  Reports per-cell steps and K_D, wall
+    times, the network's error against the converged fields and, with
+    chunk > 0, |U_x / U_x* - 1| every chunk steps for each start."""
+    cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
+    b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
+    out = dict(n_cells=len(packs), edge=edge, tau=tau, delta_rho=delta_rho, tol=tol)
+    try:
+        out["launch_shape"] = list(b.autotune(steps=5)[:2])
+        fluid = b.mask() == 0
+        t0 = time.perf_counter()
+        pred = np.stack([net.predict(fluid[i]) for i in range(len(packs))])
+        out["predict_seconds"] = time.perf_counter() - t0
+        lin = W.linear_density(fluid.shape, delta_rho, fluid)
+        wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
+        wr = [W.warm_fields(pred[i], delta_rho, tau, fluid[i], use_density=True)
+              for i in range(len(packs))]
+        starts = {
+            "rest": (None, None),
+            "linear_density": (lin, None),
+            "network_u": (lin, np.stack([w[1] for w in wu], axis=1)),
+            "network_u_rho": (np.stack([w[0] for w in wr]), np.stack([w[1] for w in wr], axis=1)),
+        }
+        conv = None
+        for name, start in list(starts.items()) + [("converged_fields", None)]:
+            if name == "converged_fields":
+                start = conv
+            b.init_equilibrium(*start)
+            out[name] = _run(b, tol, max_steps, log, name)
+            if name == "rest":
+                drho, u = b.macroscopic()
+                conv = (drho, u)
+                eu, ep = [], []
+                for i in range(len(packs)):
+                    t = W.fields_to_targets(drho[i], u[:, i], delta_rho, tau, fluid[i])
+                    f = fluid[i]
+                    eu.append(float(np.linalg.norm((pred[i][..., :3] - t[..., :3])[f])
+                                    / np.linalg.norm(t[..., :3][f])))
+                    ep.append(float(np.linalg.norm((pred[i][..., 3] - t[..., 3])[f])
+                                    / np.linalg.norm(t[..., 3][f])))
+                out["network_rel_error_u"] = eu
+                out["network_rel_error_p"] = ep
+                Ustar = np.array(out["rest"]["U"])
+                Upred = np.array([(pred[i][..., 0] * fluid[i]).sum() / fluid[i].size
+                                  for i in range(len(packs))]) * (
+                    observables.pressure_gradient(delta_rho, edge) / observables.viscosity(tau))
+                out["network_rel_error_U"] = (Upred / Ustar - 1).tolist()
+        if chunk > 0:
+            Ustar = np.array(out["rest"]["U"])
+            for name in ("rest", "network_u", "converged_fields"):
+                st = conv if name == "converged_fields" else starts[name]
+                traj = _trajectory(b, st, chunk, n_chunks)
+                out[name]["trajectory_rel_error"] = np.abs(traj / Ustar[None] - 1).tolist()
+                out[name]["trajectory_chunk"] = chunk
+    finally:
+        b.close()
+    cold = np.array(out["rest"]["steps"], float)
+    kc = np.array(out["rest"]["K_D"])
+    for name in ("linear_density", "network_u", "network_u_rho", "converged_fields"):
+        s = np.array(out[name]["steps"], float)
+        k = np.array(out[name]["K_D"])
+        out[name]["step_ratio_median"] = float(np.median(s / cold))
+        out[name]["step_ratio_mean"] = float(np.mean(s / cold))
+        out[name]["total_step_ratio"] = float(s.sum() / cold.sum())
+        out[name]["max_rel_K_diff"] = float(np.max(np.abs(k / kc - 1)))
+    out["porosity"] = [float(f.mean()) for _, f in packs]
+    out["radius"] = [float(sp[0, 3]) for sp, _ in packs]
+    out["n_spheres"] = [int(len(sp)) for sp, _ in packs]
+    return out
+
+
+# -------------------------------------------------------------------- CLI
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    tr = sub.add_parser("train")
+    tr.add_argument("--cells", type=int, default=4096)
+    tr.add_argument("--edge", type=int, default=64)
+    tr.add_argument("--per-batch", type=int, default=256)
+    tr.add_argument("--seed", type=int, default=5000)
+    tr.add_argument("--tau", type=float, default=1.0)
+    tr.add_argument("--delta-rho", type=float, default=1e-5)
+    tr.add_argument("--tol", type=float, default=1e-6)
+    tr.add_argument("--max-steps", type=int, default=50000)
+    tr.add_argument("--widths", default="32,64,128,256")
+    tr.add_argument("--epochs", type=int, default=8)
+    tr.add_argument("--minibatch", type=int, default=4)
+    tr.add_argument("--lr", type=float, default=1e-3)
+    tr.add_argument("--time-limit", type=float, default=1e30)
+    tr.add_argument("--out", required=True)
+    tr.add_argument("--history")
+    ev = sub.add_parser("evaluate")
+    ev.add_argument("--weights", required=True)
+    ev.add_argument("--cells", type=int, default=64)
+    ev.add_argument("--edge", type=int, default=128)
+    ev.add_argument("--seed", type=int, default=5)
+    ev.add_argument("--tau", type=float, default=0.8)
+    ev.add_argument("--delta-rho", type=float, default=1e-5)
+    ev.add_argument("--tol", type=float, default=1e-8)
+    ev.add_argument("--max-steps", type=int, default=200000)
+    ev.add_argument("--chunk", type=int, default=0)
+    ev.add_argument("--n-chunks", type=int, default=0)
+    ev.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        t0 = time.perf_counter()
+        fluid, targets = training_set(a.cells, a.edge, a.seed, a.per_batch, a.tau, a.delta_rho,
+                                      a.tol, a.max_steps)
+        gen = time.perf_counter() - t0
+        _log(f"[train-data] {len(fluid)} cells in {gen:.0f} s")
+        net = W.UNet(widths=tuple(int(v) for v in a.widths.split(",")), seed=a.seed)
+        _log(f"[train] {net.n_params()} parameters")
+        hist = train(net, fluid, targets, epochs=a.epochs, minibatch=a.minibatch, lr=a.lr,
+                     time_limit=a.time_limit - gen, checkpoint=a.out)
+        net.save(a.out)
+        if a.history:
+            with open(a.history, "w") as fh:
+                json.dump(dict(cells=len(fluid), generate_seconds=gen, params=net.n_params(),
+                               scale=net.scale, history=hist, args=vars(a)), fh, indent=1)
+    else:
+        net = W.UNet.load(a.weights)
+        packs = draw_packs(a.cells, a.edge, a.seed, EVAL_SPHERES)
+        res = evaluate(net, packs, a.edge, tau=a.tau, delta_rho=a.delta_rho, tol=a.tol,
+                       max_steps=a.max_steps, chunk=a.chunk, n_chunks=a.n_chunks)
+        res["params"] = net.n_params()
+        with open(a.out, "w") as fh:
+            json.dump(res, fh, indent=1)
+        for name in ("linear_density", "network_u", "network_u_rho", "converged_fields"):
+            _log(f"[eval] {name}: median step ratio {res[name]['step_ratio_median']:.3f}, "
+                 f"total {res[name]['total_step_ratio']:.3f}, "
+                 f"max |K/K_rest - 1| {res[name]['max_rel_K_diff']:.2e}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

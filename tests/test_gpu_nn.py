@@ -234,20 +234,25 @@ def test_unet_gradients_match_cpu_twin(ctx):
 
 
 def test_unet_training_reduces_loss(ctx):
-    """A few Adam steps on a fixed target lower the loss."""
+    """Adam steps on a learnable target lower the loss.  The network is
+    translation-equivariant, so the target is a local function of the mask:
+    the fluid fraction of each voxel's 3x3x3 neighbourhood, on fluid voxels."""
+    from scipy import ndimage
+
     net = W.UNet(widths=(8, 16, 16, 32), seed=9, device="cuda")
     rng = np.random.default_rng(10)
     shape = (2, 16, 16, 16)
     fluid = (rng.uniform(size=shape) > 0.3).astype(np.float32)
-    target = (np.sin(np.arange(16) / 3.0)[None, None, None, :, None]
-              * fluid[..., None] * np.ones(3)).astype(np.float32)
+    local = np.stack([ndimage.uniform_filter(f, size=3, mode="wrap") for f in fluid])
+    target = (local * fluid)[..., None] * np.array([1.0, -0.5, 0.25])
+    target = target.astype(np.float32)
     x = W.network_input(net.ctx, fluid)
     t, wgt = _f_dev(ctx, target), _f_dev(ctx, fluid)
     losses = []
-    for _ in range(30):
+    for _ in range(40):
         out = net.forward(x)
         loss, g = net.loss(out, t, wgt, 3.0 * fluid.sum())
         net.backward(g)
-        net.adam_step(3e-3)
+        net.adam_step(1e-2)
         losses.append(loss)
-    assert losses[-1] < 0.5 * losses[0], losses
+    assert losses[-1] < 0.3 * losses[0], losses

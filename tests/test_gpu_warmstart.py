@@ -1,0 +1,70 @@
+"""The learned warm start end to end at a small size: training fields from the
+batch solver, a small U-Net trained by the library's kernels, and held-out
+packs run to a 1e-8 residual from rest and from the network's prediction.
+The warm start must need fewer steps and reach the same permeability."""
+import numpy as np
+import pytest
+
+from paper_1508_02960_amd import warmstart as W
+from paper_1508_02960_amd import warmstart_study as S
+
+pytestmark = pytest.mark.gpu
+
+EDGE = 32
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    packs = S.draw_packs(48, EDGE, 11, S.TRAIN_SPHERES)
+    t, fluid, res = S.solve_stokes(packs, EDGE, tau=1.0, delta_rho=1e-5, tol=1e-6,
+                                   max_steps=40000)
+    ok = np.array([s == "converged" for s in res["status"]])
+    assert ok.sum() >= 40, res["status"]
+    net = W.UNet(widths=(16, 32, 32, 64), seed=1, device="cuda")
+    f = torch.from_numpy(fluid[ok].astype(np.uint8)).cuda()
+    tg = torch.from_numpy(t[ok]).cuda()
+    hist = S.train(net, f, tg, epochs=20, minibatch=4, lr=3e-3, val_frac=0.1, log=print)
+    return net, hist
+
+
+def test_training_lowers_held_out_error(trained):
+    _, hist = trained
+    assert hist[-1]["val_rel_u"] < 0.5 * hist[0]["val_rel_u"] or hist[-1]["val_rel_u"] < 0.3
+    assert hist[-1]["loss"] < hist[0]["loss"]
+
+
+def _steps_to(traj, level, chunk):
+    """Steps after which |U/U* - 1| stays below level, per cell."""
+    out = []
+    for col in np.asarray(traj).T:
+        above = np.nonzero(col >= level)[0]
+        out.append((above[-1] + 2 if len(above) else 1) * chunk)
+    return np.array(out)
+
+
+def test_warm_start_gains_over_rest(trained):
+    net, _ = trained
+    packs = S.draw_packs(8, EDGE, 12, S.TRAIN_SPHERES)
+    res = S.evaluate(net, packs, EDGE, tau=0.8, delta_rho=1e-5, tol=1e-8, max_steps=100000,
+                     log=print, chunk=100, n_chunks=40)
+    for k in ("network_u", "network_u_rho", "converged_fields"):
+        print(k, {q: res[k][q] for q in ("step_ratio_median", "total_step_ratio",
+                                         "max_rel_K_diff")})
+    print("network error u", np.median(res["network_rel_error_u"]), "U",
+          np.abs(res["network_rel_error_U"]))
+    rest = res["rest"]["trajectory_rel_error"]
+    warm = res["network_u"]["trajectory_rel_error"]
+    s_rest = _steps_to(rest, 1e-3, 100)
+    s_warm = _steps_to(warm, 1e-3, 100)
+    print("steps to 1e-3 of U*: rest", s_rest, "warm", s_warm)
+    assert all(s == "converged" for s in res["rest"]["status"])
+    assert all(s == "converged" for s in res["network_u"]["status"])
+    # the plain iteration decides K: the same permeability from either start
+    assert res["network_u"]["max_rel_K_diff"] <= 1e-3
+    # the prediction starts much closer to the steady mean flow ...
+    assert np.median(np.array(warm[0]) / np.array(rest[0])) < 0.3
+    # ... and reaches 0.1 % of it in fewer steps
+    assert np.median(s_warm / s_rest) < 1.0
