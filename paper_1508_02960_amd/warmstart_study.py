@@ -100,18 +100,24 @@ def solve_stokes(packs, edge: int, tau: float, delta_rho: float, tol: float, max
 
 
 def training_set(n_cells: int, edge: int, seed: int, per_batch: int, tau: float,
-                 delta_rho: float, tol: float, max_steps: int, device=None, log=_log):
+                 delta_rho: float, tol: float, max_steps: int, device=None, log=_log,
+                 time_limit: float = 1e30, n_range=TRAIN_SPHERES):
     """Device tensors (fluid uint8 (n, e, e, e), targets float32 (n, e, e, e, 4))
-    of converged cells, from batches of per_batch cells with seeds seed, seed+1..."""
+    of converged cells, from batches of per_batch cells with seeds seed, seed+1...
+    Stops early (after a whole batch) once time_limit seconds have passed."""
     import torch
 
     dev = torch.device(device if device is not None else "cuda")
     fl, tg = [], []
     b = 0
+    t_start = time.perf_counter()
     while sum(len(f) for f in fl) < n_cells:
+        if b > 0 and time.perf_counter() - t_start > time_limit:
+            log(f"[train-data] time limit: {sum(len(f) for f in fl)} cells")
+            break
         t0 = time.perf_counter()
         want = min(per_batch, n_cells - sum(len(f) for f in fl))
-        packs = draw_packs(want, edge, seed + b, TRAIN_SPHERES)
+        packs = draw_packs(want, edge, seed + b, n_range)
         t, fluid, res = solve_stokes(packs, edge, tau, delta_rho, tol, max_steps, device)
         ok = np.array([s == "converged" for s in res["status"]])
         fl.append(torch.from_numpy(fluid[ok].astype(np.uint8)).to(dev))
@@ -161,7 +167,7 @@ def train(net, fluid, targets, *, epochs: int, minibatch: int, lr: float, val_fr
     steps_per_epoch = max(1, n_tr // minibatch)
     total = epochs * steps_per_epoch
     warm = min(100, total // 10 + 1)
-    t0 = time.perf_counter()
+    t0 = t_log = time.perf_counter()
     history = []
     step = 0
     for ep in range(epochs):
@@ -174,12 +180,20 @@ def train(net, fluid, targets, *, epochs: int, minibatch: int, lr: float, val_fr
             wt = f.float()
             loss, g = net.loss(out, tn[idx], wt, 4.0 * float(wt.sum().item()), sync=False)
             net.backward(g)
-            frac = step / max(total - 1, 1)
+            # the schedule ends at the last step or at the time limit
+            frac = min(1.0, max(step / max(total - 1, 1),
+                                (time.perf_counter() - t0) / time_limit))
             rate = lr * min(1.0, (step + 1) / warm) * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * frac)))
             net.adam_step(rate)
             acc += loss
             step += 1
-        train_loss = float(acc.item()) / steps_per_epoch
+            if time.perf_counter() - t_log > 60:
+                t_log = time.perf_counter()
+                log(f"[train] epoch {ep} step {j + 1}/{steps_per_epoch}, "
+                    f"{t_log - t0:.0f} s")
+            if time.perf_counter() - t0 > time_limit:
+                break
+        train_loss = float(acc.item()) / max(1, j + 1)
         ev = rel_errors(net, fluid[n_tr:], tn[n_tr:]) if n_val else (float("nan"),) * 2
         el = time.perf_counter() - t0
         history.append(dict(epoch=ep, loss=train_loss, val_rel_u=ev[0], val_rel_p=ev[1],
@@ -220,34 +234,41 @@ def _trajectory(b, start, chunk, n_chunks):
     return np.array(traj)  # (n_chunks, n_cells)
 
 
-def evaluate(net, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
-             device=None, log=_log, chunk: int = 0, n_chunks: int = 0):
+def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
+             device=None, log=_log, chunk: int = 0, n_chunks: int = 0,
+             with_density: bool = False):
     """Starts of the same packs, each run to tol by the plain iteration:
     rest; linear density; the network's velocity (wall layer at rest) with
-    the linear density; the same plus the network's density fluctuation;
-    and, as the bound of any equilibrium-initialised warm start, the
+    the linear density; with with_density the same plus the network's
+    density fluctuation; and, as the bound of any equilibrium-initialised warm start, the
     converged fields of the rest run.  Reports per-cell steps and K_D, wall
     times, the network's error against the converged fields and, with
-    chunk > 0, |U_x / U_x* - 1| every chunk steps for each start."""
+    chunk > 0, |U_x / U_x* - 1| every chunk steps for each start.  nets is
+    a network or a dict name -> network; the starts of a network named n
+    are network_u[n] and network_u_rho[n] (no suffix for a single one)."""
+    if not isinstance(nets, dict):
+        nets = {"": nets}
     cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
     b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
     out = dict(n_cells=len(packs), edge=edge, tau=tau, delta_rho=delta_rho, tol=tol)
     try:
         out["launch_shape"] = list(b.autotune(steps=5)[:2])
         fluid = b.mask() == 0
-        t0 = time.perf_counter()
-        pred = np.stack([net.predict(fluid[i]) for i in range(len(packs))])
-        out["predict_seconds"] = time.perf_counter() - t0
         lin = W.linear_density(fluid.shape, delta_rho, fluid)
-        wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
-        wr = [W.warm_fields(pred[i], delta_rho, tau, fluid[i], use_density=True)
-              for i in range(len(packs))]
-        starts = {
-            "rest": (None, None),
-            "linear_density": (lin, None),
-            "network_u": (lin, np.stack([w[1] for w in wu], axis=1)),
-            "network_u_rho": (np.stack([w[0] for w in wr]), np.stack([w[1] for w in wr], axis=1)),
-        }
+        starts = {"rest": (None, None), "linear_density": (lin, None)}
+        preds = {}
+        for tag, net in nets.items():
+            t0 = time.perf_counter()
+            pred = np.stack([net.predict(fluid[i]) for i in range(len(packs))])
+            out["predict_seconds" + tag] = time.perf_counter() - t0
+            preds[tag] = pred
+            wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
+            starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
+            if with_density:
+                wr = [W.warm_fields(pred[i], delta_rho, tau, fluid[i], use_density=True)
+                      for i in range(len(packs))]
+                starts["network_u_rho" + tag] = (np.stack([w[0] for w in wr]),
+                                                 np.stack([w[1] for w in wr], axis=1))
         conv = None
         for name, start in list(starts.items()) + [("converged_fields", None)]:
             if name == "converged_fields":
@@ -257,24 +278,22 @@ def evaluate(net, packs, edge: int, *, tau: float, delta_rho: float, tol: float,
             if name == "rest":
                 drho, u = b.macroscopic()
                 conv = (drho, u)
-                eu, ep = [], []
-                for i in range(len(packs)):
-                    t = W.fields_to_targets(drho[i], u[:, i], delta_rho, tau, fluid[i])
-                    f = fluid[i]
-                    eu.append(float(np.linalg.norm((pred[i][..., :3] - t[..., :3])[f])
-                                    / np.linalg.norm(t[..., :3][f])))
-                    ep.append(float(np.linalg.norm((pred[i][..., 3] - t[..., 3])[f])
-                                    / np.linalg.norm(t[..., 3][f])))
-                out["network_rel_error_u"] = eu
-                out["network_rel_error_p"] = ep
-                Ustar = np.array(out["rest"]["U"])
-                Upred = np.array([(pred[i][..., 0] * fluid[i]).sum() / fluid[i].size
-                                  for i in range(len(packs))]) * (
-                    observables.pressure_gradient(delta_rho, edge) / observables.viscosity(tau))
-                out["network_rel_error_U"] = (Upred / Ustar - 1).tolist()
+                for tag, pred in preds.items():
+                    eu, ep, eU = [], [], []
+                    for i in range(len(packs)):
+                        t = W.fields_to_targets(drho[i], u[:, i], delta_rho, tau, fluid[i])
+                        f = fluid[i]
+                        eu.append(float(np.linalg.norm((pred[i][..., :3] - t[..., :3])[f])
+                                        / np.linalg.norm(t[..., :3][f])))
+                        ep.append(float(np.linalg.norm((pred[i][..., 3] - t[..., 3])[f])
+                                        / np.linalg.norm(t[..., 3][f])))
+                        eU.append(float((pred[i][..., 0] * f).sum() / (t[..., 0] * f).sum() - 1))
+                    out["network_rel_error_u" + tag] = eu
+                    out["network_rel_error_p" + tag] = ep
+                    out["network_rel_error_U" + tag] = eU
         if chunk > 0:
             Ustar = np.array(out["rest"]["U"])
-            for name in ("rest", "network_u", "converged_fields"):
+            for name in ["rest", "converged_fields"] + ["network_u" + t for t in nets]:
                 st = conv if name == "converged_fields" else starts[name]
                 traj = _trajectory(b, st, chunk, n_chunks)
                 out[name]["trajectory_rel_error"] = np.abs(traj / Ustar[None] - 1).tolist()
@@ -283,7 +302,7 @@ def evaluate(net, packs, edge: int, *, tau: float, delta_rho: float, tol: float,
         b.close()
     cold = np.array(out["rest"]["steps"], float)
     kc = np.array(out["rest"]["K_D"])
-    for name in ("linear_density", "network_u", "network_u_rho", "converged_fields"):
+    for name in [n for n in out if isinstance(out[n], dict) and "steps" in out[n] and n != "rest"]:
         s = np.array(out[name]["steps"], float)
         k = np.array(out[name]["K_D"])
         out[name]["step_ratio_median"] = float(np.median(s / cold))
@@ -311,14 +330,19 @@ def main(argv=None) -> int:
     tr.add_argument("--tol", type=float, default=1e-6)
     tr.add_argument("--max-steps", type=int, default=50000)
     tr.add_argument("--widths", default="32,64,128,256")
+    tr.add_argument("--spheres", default="1,4", help="sphere count range per cell")
     tr.add_argument("--epochs", type=int, default=8)
     tr.add_argument("--minibatch", type=int, default=4)
     tr.add_argument("--lr", type=float, default=1e-3)
     tr.add_argument("--time-limit", type=float, default=1e30)
+    tr.add_argument("--data-time-limit", type=float, default=1e30)
     tr.add_argument("--out", required=True)
     tr.add_argument("--history")
     ev = sub.add_parser("evaluate")
-    ev.add_argument("--weights", required=True)
+    ev.add_argument("--weights", required=True, nargs="+",
+                    help="network weights, as path or name=path")
+    ev.add_argument("--with-density", action="store_true")
+    ev.add_argument("--spheres", default="8,27", help="sphere count range per cell")
     ev.add_argument("--cells", type=int, default=64)
     ev.add_argument("--edge", type=int, default=128)
     ev.add_argument("--seed", type=int, default=5)
@@ -329,11 +353,29 @@ def main(argv=None) -> int:
     ev.add_argument("--chunk", type=int, default=0)
     ev.add_argument("--n-chunks", type=int, default=0)
     ev.add_argument("--out", required=True)
+    rp = sub.add_parser("report")
+    rp.add_argument("--train", nargs="*", default=[], help="title=history.json")
+    rp.add_argument("--eval", nargs="*", default=[], help="title=eval.json")
+    rp.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "report":
+        parts = []
+        for item in a.train:
+            title, _, path = item.partition("=")
+            with open(path) as fh:
+                parts.append(report_training(json.load(fh), title))
+        for item in a.eval:
+            title, _, path = item.partition("=")
+            with open(path) as fh:
+                parts.append(report_eval(json.load(fh), title))
+        with open(a.out, "w") as fh:
+            fh.write("\n".join(parts))
+        return 0
     if a.cmd == "train":
         t0 = time.perf_counter()
         fluid, targets = training_set(a.cells, a.edge, a.seed, a.per_batch, a.tau, a.delta_rho,
-                                      a.tol, a.max_steps)
+                                      a.tol, a.max_steps, time_limit=a.data_time_limit,
+                                      n_range=tuple(int(v) for v in a.spheres.split(",")))
         gen = time.perf_counter() - t0
         _log(f"[train-data] {len(fluid)} cells in {gen:.0f} s")
         net = W.UNet(widths=tuple(int(v) for v in a.widths.split(",")), seed=a.seed)
@@ -346,18 +388,94 @@ def main(argv=None) -> int:
                 json.dump(dict(cells=len(fluid), generate_seconds=gen, params=net.n_params(),
                                scale=net.scale, history=hist, args=vars(a)), fh, indent=1)
     else:
-        net = W.UNet.load(a.weights)
-        packs = draw_packs(a.cells, a.edge, a.seed, EVAL_SPHERES)
-        res = evaluate(net, packs, a.edge, tau=a.tau, delta_rho=a.delta_rho, tol=a.tol,
-                       max_steps=a.max_steps, chunk=a.chunk, n_chunks=a.n_chunks)
-        res["params"] = net.n_params()
+        nets = {}
+        for w in a.weights:
+            name, _, path = w.rpartition("=")
+            nets[f"[{name}]" if name else ""] = W.UNet.load(path)
+        packs = draw_packs(a.cells, a.edge, a.seed, tuple(int(v) for v in a.spheres.split(",")))
+        res = evaluate(nets, packs, a.edge, tau=a.tau, delta_rho=a.delta_rho, tol=a.tol,
+                       max_steps=a.max_steps, chunk=a.chunk, n_chunks=a.n_chunks,
+                       with_density=a.with_density)
+        res["params"] = {k: n.n_params() for k, n in nets.items()}
         with open(a.out, "w") as fh:
             json.dump(res, fh, indent=1)
-        for name in ("linear_density", "network_u", "network_u_rho", "converged_fields"):
+        for name in [n for n in res if isinstance(res[n], dict) and "step_ratio_median" in res[n]]:
             _log(f"[eval] {name}: median step ratio {res[name]['step_ratio_median']:.3f}, "
                  f"total {res[name]['total_step_ratio']:.3f}, "
                  f"max |K/K_rest - 1| {res[name]['max_rel_K_diff']:.2e}")
     return 0
+
+
+
+# ----------------------------------------------------------------- report
+
+def steps_to_accuracy(traj, level: float, chunk: int) -> np.ndarray:
+    """Per cell, the steps after which |U/U* - 1| stays below level (NaN if
+    it is still above at the end of the trajectory)."""
+    out = []
+    for col in np.asarray(traj).T:
+        above = np.nonzero(col >= level)[0]
+        if len(above) == 0:
+            out.append(chunk)
+        elif above[-1] + 1 < len(col):
+            out.append((above[-1] + 2) * chunk)
+        else:
+            out.append(np.nan)
+    return np.array(out, float)
+
+
+def report_eval(res: dict, title: str) -> str:
+    """Markdown tables of one evaluation."""
+    names = ["rest"] + [n for n in res if isinstance(res[n], dict) and "step_ratio_median" in res[n]]
+    lines = [f"### {title}", "",
+             f"{res['n_cells']} cells of {res['edge']}^3, {min(res['n_spheres'])}-{max(res['n_spheres'])} "
+             f"spheres, porosity {min(res['porosity']):.2f}-{max(res['porosity']):.2f}, radius "
+             f"{min(res['radius']):.1f}-{max(res['radius']):.1f}; tau {res['tau']}, delta_rho "
+             f"{res['delta_rho']:g}, residual tolerance {res['tol']:g}; one batch run per start.  "
+             "Network inference for all cells: " + ", ".join(
+                 f"{res[k]:.1f} s" for k in res if k.startswith("predict_seconds")) + ".", "",
+             "| start | wall time (s) | steps, median | steps / rest, median | total steps / rest "
+             "| max \\|K_D / K_D(rest) - 1\\| |",
+             "|---|---|---|---|---|---|"]
+    for n in names:
+        r = res[n]
+        if n == "rest":
+            lines.append(f"| rest | {r['seconds']:.1f} | {np.median(r['steps']):.0f} | 1 | 1 | 0 |")
+        else:
+            lines.append(f"| {n} | {r['seconds']:.1f} | {np.median(r['steps']):.0f} | "
+                         f"{r['step_ratio_median']:.3f} | {r['total_step_ratio']:.3f} | "
+                         f"{r['max_rel_K_diff']:.1e} |")
+    traj = [n for n in names if "trajectory_rel_error" in res[n]]
+    if traj:
+        lines += ["", "Steps until the superficial velocity stays within a relative error of "
+                  "U* (the converged rest-start value), median over cells:", "",
+                  "| start | 1e-2 | 1e-3 | 1e-4 | 1e-5 |", "|---|---|---|---|---|"]
+        for n in traj:
+            c = res[n]["trajectory_chunk"]
+            row = [f"{np.nanmedian(steps_to_accuracy(res[n]['trajectory_rel_error'], lv, c)):.0f}"
+                   for lv in (1e-2, 1e-3, 1e-4, 1e-5)]
+            lines.append(f"| {n} | " + " | ".join(row) + " |")
+    errs = [k for k in res if k.startswith("network_rel_error_u")]
+    if errs:
+        lines += ["", "| network | relative L2 error of u, median | of the density fluctuation | "
+                  "of U (mean flow), median \\|.\\| |", "|---|---|---|---|"]
+        for k in errs:
+            tag = k[len("network_rel_error_u"):] or "-"
+            lines.append(f"| {tag} | {np.median(res[k]):.3f} | "
+                         f"{np.median(res['network_rel_error_p' + k[len('network_rel_error_u'):]]):.3f} | "
+                         f"{np.median(np.abs(res['network_rel_error_U' + k[len('network_rel_error_u'):]])):.3f} |")
+    return "\n".join(lines) + "\n"
+
+
+def report_training(hist: dict, title: str) -> str:
+    h = hist["history"]
+    a = hist["args"]
+    return (f"### {title}\n\n{hist['cells']} cells of {a['edge']}^3 ({a.get('spheres', '1,4')} spheres), solved "
+            f"to {a['tol']:g} at tau {a['tau']} in {hist['generate_seconds']:.0f} s; "
+            f"{hist['params']} parameters, {len(h)} epochs of Adam (minibatch {a['minibatch']}, "
+            f"lr {a['lr']:g}) in {h[-1]['seconds']:.0f} s; held-out relative error after the first "
+            f"and last epoch: velocity {h[0]['val_rel_u']:.3f} -> {h[-1]['val_rel_u']:.3f}, "
+            f"density fluctuation {h[0]['val_rel_p']:.3f} -> {h[-1]['val_rel_p']:.3f}.\n")
 
 
 if __name__ == "__main__":

@@ -50,7 +50,7 @@ def test_warm_start_gains_over_rest(trained):
     packs = S.draw_packs(8, EDGE, 12, S.TRAIN_SPHERES)
     res = S.evaluate(net, packs, EDGE, tau=0.8, delta_rho=1e-5, tol=1e-8, max_steps=100000,
                      log=print, chunk=100, n_chunks=40)
-    for k in ("network_u", "network_u_rho", "converged_fields"):
+    for k in ("network_u", "converged_fields"):
         print(k, {q: res[k][q] for q in ("step_ratio_median", "total_step_ratio",
                                          "max_rel_K_diff")})
     print("network error u", np.median(res["network_rel_error_u"]), "U",
