@@ -375,24 +375,49 @@ static double jump(const orc_params* p, int px, int k) {
   return 0.0;
 }
 
-/* Value of population k read at the unwrapped node (px, py, pz). */
+static int wrap_any(int i, int n) { return ((i % n) + n) % n; }
+
+/* Value of population k read at the unwrapped node (px, py, pz), with the
+ * density jump when the read crosses the x-periodic plane. */
 static double read_pop(const orc_params* p, const double* g, int k, int px,
                        int py, int pz) {
   int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
-  int64_t c = cell_of(p, wrap(px, p->nx), wrap(py, p->ny), wrap(pz, p->nz));
+  int64_t c = cell_of(p, wrap_any(px, p->nx), wrap_any(py, p->ny), wrap_any(pz, p->nz));
   return g[k * ncell + c] + jump(p, px, k);
 }
 
-/* Incoming value of direction k at fluid node (x,y,z) whose pull source
- * x - e_k is solid.  j = kbar points into the wall; the link is (x, j) with
- * wall distance q.  eq. (noslip): f_k(x, t+1) = ftilde_j(x, t).  eq. (CLI)
- * with the paper's k -> j and kbar -> k, x_f1 = x, x_f2 = x - e_j = x + e_k:
- *   f_k(x, t+1) = a ftilde_j(x_f2) - a ftilde_k(x) + ftilde_j(x),
- *   a = (1 - 2q) / (1 + 2q).
- * The formula is affine with coefficients summing to one, so it applies to
- * the deviations g = f - w unchanged (w_j = w_k).
- * READING: CLI needs x_f2 to be fluid; when it is solid the link falls back to
- * simple bounce-back. */
+/* Is the node m steps from (x,y,z) along e_k solid? */
+static int solid_along(const orc_params* p, const uint8_t* mask, int x, int y, int z,
+                       int k, int m) {
+  return mask[cell_of(p, wrap_any(x + m * VEL[k][0], p->nx),
+                      wrap_any(y + m * VEL[k][1], p->ny),
+                      wrap_any(z + m * VEL[k][2], p->nz))] != 0;
+}
+
+/* Density deviation and velocity of the stored state at cell c (moments of
+ * the post-collision populations, which equal those before collision). */
+static void stored_moments(const orc_params* p, const double* g, int64_t c,
+                           double* drho, double u[3]) {
+  int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+  *drho = 0.0;
+  u[0] = u[1] = u[2] = 0.0;
+  for (int k = 0; k < 19; ++k) {
+    double v = g[k * ncell + c];
+    *drho += v;
+    for (int a = 0; a < 3; ++a) u[a] += VEL[k][a] * v;
+  }
+}
+
+/* Incoming value of direction k at fluid node x = (x,y,z) whose pull source
+ * x - e_k is solid.  In the paper's notation the link direction into the
+ * wall is k there (j = kbar here), the unknown is f_kbar (f_k here),
+ * x_f1 = x, x_f2 = x + e_k and x_f3 = x + 2 e_k (away from the wall), and
+ * the right-hand sides are post-collision values at time t_n (the stored
+ * state g).  A scheme that needs a node that is solid falls back to the
+ * closest scheme with fewer nodes: x_f2 solid -> eq. (noslip) (LIBB and QIBB
+ * for q >= 1/2 need x_f1 only and keep LIBB's q >= 1/2 branch); x_f3 solid
+ * -> LIBB (from QIBB) or CLI (from MR).  Values read across the x-periodic
+ * plane carry the density jump. */
 static double wall_value(const orc_params* p, const uint8_t* mask,
                          const double* Q, const double* g, int x, int y, int z,
                          int k) {
@@ -401,14 +426,78 @@ static double wall_value(const orc_params* p, const uint8_t* mask,
   int j = opposite_of(k);
   double own_j = g[j * ncell + c];
   if (p->wall == ORC_SBB) return own_j;
-  int x2 = x + VEL[k][0], y2 = y + VEL[k][1], z2 = z + VEL[k][2];
-  int64_t c2 = cell_of(p, wrap(x2, p->nx), wrap(y2, p->ny), wrap(z2, p->nz));
-  if (mask[c2]) return own_j;
-  double q = Q[j * ncell + c];
-  double a = (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
-  double far_j = read_pop(p, g, j, x2, y2, z2);
   double own_k = g[k * ncell + c];
-  return a * far_j - a * own_k + own_j;
+  double q = Q[j * ncell + c];
+  int f2 = !solid_along(p, mask, x, y, z, k, 1);
+  int f3 = f2 && !solid_along(p, mask, x, y, z, k, 2);
+  int x2 = x + VEL[k][0], y2 = y + VEL[k][1], z2 = z + VEL[k][2];
+  int x3 = x + 2 * VEL[k][0], y3 = y + 2 * VEL[k][1], z3 = z + 2 * VEL[k][2];
+  int wall = p->wall;
+  if (wall == ORC_MR && !f3) wall = ORC_CLI;
+  if (wall == ORC_QIBB && (q < 0.5 ? !f3 : !f2)) wall = ORC_LIBB;
+  switch (wall) {
+    case ORC_CLI: {
+      /* eq. (CLI): a = (1 - 2q) / (1 + 2q) */
+      if (!f2) return own_j;
+      double a = (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
+      return a * read_pop(p, g, j, x2, y2, z2) - a * own_k + own_j;
+    }
+    case ORC_LIBB:
+      /* eq. (LIBB) */
+      if (q < 0.5) {
+        if (!f2) return own_j;
+        return (1.0 - 2.0 * q) * read_pop(p, g, j, x2, y2, z2) + 2.0 * q * own_j;
+      }
+      return (1.0 - 1.0 / (2.0 * q)) * own_k + own_j / (2.0 * q);
+    case ORC_QIBB:
+      /* eq. (QIBB) */
+      if (q < 0.5)
+        return q * (1.0 + 2.0 * q) * own_j +
+               (1.0 - 4.0 * q * q) * read_pop(p, g, j, x2, y2, z2) -
+               q * (1.0 - 2.0 * q) * read_pop(p, g, j, x3, y3, z3);
+      return (2.0 * q - 1.0) / q * own_k + own_j / (q * (2.0 * q + 1.0)) +
+             (1.0 - 2.0 * q) / (2.0 * q + 1.0) * read_pop(p, g, k, x2, y2, z2);
+    case ORC_IEBB: {
+      /* eqs. (fstar) and (IEBB): wall velocity u_bf, auxiliary population
+       * f*_j(x_b) with the local density deviation of x_f1, and the mixing
+       * weight X with omega = 1/tau (omega+ of TRT, s_nu of MRT) */
+      double drho1, u1[3], ubf[3], X;
+      stored_moments(p, g, c, &drho1, u1);
+      if (q < 0.5) {
+        double d2;
+        if (!f2) return own_j;
+        stored_moments(p, g, cell_of(p, wrap_any(x2, p->nx), wrap_any(y2, p->ny),
+                                     wrap_any(z2, p->nz)), &d2, ubf);
+        X = (2.0 * q - 1.0) / (p->tau - 2.0);
+      } else {
+        for (int a = 0; a < 3; ++a) ubf[a] = (1.0 - 3.0 / (2.0 * q)) * u1[a];
+        X = (2.0 * q - 1.0) / (p->tau + 0.5);
+      }
+      double eub = 0.0, eu1 = 0.0, uu = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        eub += VEL[j][a] * ubf[a];
+        eu1 += VEL[j][a] * u1[a];
+        uu += u1[a] * u1[a];
+      }
+      double fstar = W_T[j] * (drho1 + 3.0 * eub + 4.5 * eu1 * eu1 - 1.5 * uu);
+      return (1.0 - X) * own_j + X * fstar;
+    }
+    default: {
+      /* ORC_MR, eq. (MR); kappa_1 = (1 - 2q - 2q^2)/(1 + q)^2 (the printed
+       * (1 + 2q)^2 breaks exactness for linear profiles), kappa_2 = q^2/(1 + q)^2 */
+      if (!f2) return own_j;
+      double d = (1.0 + q) * (1.0 + q);
+      double k1 = (1.0 - 2.0 * q - 2.0 * q * q) / d, k2 = q * q / d;
+      return k1 * read_pop(p, g, j, x2, y2, z2) + k2 * read_pop(p, g, j, x3, y3, z3) -
+             k1 * own_k - k2 * read_pop(p, g, k, x2, y2, z2) + own_j;
+    }
+  }
+}
+
+double orc_wall_value(const orc_params* p, const uint8_t* mask, const double* Q,
+                      const double* g, int32_t x, int32_t y, int32_t z, int32_t k) {
+  ensure_tables();
+  return wall_value(p, mask, Q, g, x, y, z, k);
 }
 
 /* Fused step in the paper's order (Sec. 2: first streaming, then collision):

@@ -29,7 +29,9 @@ extern "C" {
 #endif
 
 enum { ORC_SRT = 0, ORC_TRT = 1, ORC_MRT = 2 };
-enum { ORC_SBB = 0, ORC_CLI = 1 };
+/* Wall rules of Sec. 2.2.1: eq. (noslip), eq. (CLI), eq. (LIBB), eq. (QIBB),
+ * eqs. (fstar)-(IEBB) and eq. (MR) (with the (1+q)^2 denominator of kappa_1). */
+enum { ORC_SBB = 0, ORC_CLI = 1, ORC_LIBB = 2, ORC_QIBB = 3, ORC_IEBB = 4, ORC_MR = 5 };
 
 typedef struct {
   int32_t nx, ny, nz;
@@ -81,6 +83,12 @@ int64_t orc_wall_q(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
  * u0 (3*ncell, component-major u0[a*ncell + c]) may be NULL (=0). */
 void orc_init(const orc_params* p, const uint8_t* mask, const double* drho0,
               const double* u0, double* g);
+
+/* Incoming value of direction k at fluid node (x,y,z) whose pull source
+ * x - e_k is solid, given by the domain's wall rule from the stored
+ * post-collision state g (deviations). */
+double orc_wall_value(const orc_params* p, const uint8_t* mask, const double* Q,
+                      const double* g, int32_t x, int32_t y, int32_t z, int32_t k);
 
 /* One fused stream-then-collide step: gout <- step(g). */
 void orc_step(const orc_params* p, const uint8_t* mask, const double* Q,

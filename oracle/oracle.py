@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 COLLISIONS = {"srt": 0, "trt": 1, "mrt": 2}
-WALLS = {"sbb": 0, "cli": 1}
+WALLS = {"sbb": 0, "cli": 1, "libb": 2, "qibb": 3, "iebb": 4, "mr": 5}
 
 
 def library_path() -> str:
@@ -70,6 +70,7 @@ def _load():
             "orc_macroscopic": (None, [P(_Params), vp, vp, vp, vp]),
             "orc_mean_velocity": (None, [P(_Params), vp, vp, vp]),
             "orc_drag": (None, [P(_Params), vp, vp, vp, vp]),
+            "orc_wall_value": (d, [P(_Params), vp, vp, vp, i32, i32, i32, i32]),
             "orc_permeability": (d, [P(_Params), d]),
             "orc_run_to_residual": (i32, [P(_Params), vp, vp, vp, vp, d, i64, i64,
                                           P(i64), P(d)]),
@@ -228,6 +229,12 @@ class Oracle:
         U = np.zeros(3)
         _load().orc_mean_velocity(C.byref(self.p), _ptr(self.mask), _ptr(self.g), _ptr(U))
         return U
+
+    def wall_value(self, x: int, y: int, z: int, k: int) -> float:
+        """Incoming value of direction k at fluid node (x, y, z) whose pull
+        source is solid, from the current state by the wall rule."""
+        return _load().orc_wall_value(C.byref(self.p), _ptr(self.mask), _ptr(self.Q),
+                                      _ptr(self.g), x, y, z, k)
 
     def drag(self) -> np.ndarray:
         F = np.zeros(3)

@@ -291,7 +291,7 @@ def _total_momentum(orc, o):
     return np.einsum("ka,kzyx->a", e.astype(float), o.g)
 
 
-@pytest.mark.parametrize("wall", ["sbb", "cli"])
+@pytest.mark.parametrize("wall", ["sbb", "cli", "libb", "qibb", "iebb", "mr"])
 @pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
 def test_momentum_exchange_identity(orc, wall, collision):
     """Per step, the fluid momentum changes by the jump injection minus the
