@@ -54,9 +54,25 @@ typedef enum {
 /* Collision operator, Sec. 2.1: eq. (SRT) with R = omega I, eq. (TRT), eq. (MRT). */
 typedef enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 } lbm_collision;
 
-/* Solid-wall rule, Sec. 2.2.1: eq. (noslip) simple bounce-back or eq. (CLI)
- * central linear interpolation with the wall distance q of each link. */
-typedef enum { LBM_WALL_SBB = 0, LBM_WALL_CLI = 1 } lbm_wall;
+/* Solid-wall rule, Sec. 2.2.1, with the wall distance q of each link:
+ * eq. (noslip) simple bounce-back, eq. (CLI) central linear interpolation,
+ * eq. (LIBB) linear and eq. (QIBB) quadratic interpolated bounce-back,
+ * eqs. (fstar)-(IEBB) interpolation/extrapolation bounce-back (omega = 1/tau
+ * in X, the local density deviation in f*; undefined at tau = 2), and
+ * eq. (MR) multi-reflection with kappa_1 = (1 - 2q - 2q^2)/(1 + q)^2 (the
+ * denominator that makes the rule exact for linear profiles).  A rule that
+ * needs a second (third) fluid node along the link where there is none falls
+ * back to simple bounce-back (LIBB from QIBB, CLI from MR); LIBB and QIBB
+ * with q >= 1/2 need only the first node.  LIBB, QIBB, IEBB and MR need FP32
+ * or FP64 storage. */
+typedef enum {
+  LBM_WALL_SBB = 0,
+  LBM_WALL_CLI = 1,
+  LBM_WALL_LIBB = 2,
+  LBM_WALL_QIBB = 3,
+  LBM_WALL_IEBB = 4,
+  LBM_WALL_MR = 5
+} lbm_wall;
 
 /* Storage precision of the populations (deviations g = f - w).  FP64 computes
  * in double; the others compute in float.  FP16 and BF16 store

@@ -23,7 +23,12 @@
 namespace lbm {
 
 enum { kSRT = 0, kTRT = 1, kMRT = 2 };
-enum { kSBB = 0, kCLI = 1 };
+// Wall templates: simple bounce-back, CLI (coefficient a in the solid slot),
+// and the general interpolated rules (LIBB, QIBB, IEBB, MR; q in the solid
+// slot, rule chosen at run time by StepParams::wall, FP32/FP64 only).
+enum { kSBB = 0, kCLI = 1, kGEN = 2 };
+// run-time rule numbers (lbm_wall)
+enum { kRuleSBB = 0, kRuleCLI = 1, kRuleLIBB = 2, kRuleQIBB = 3, kRuleIEBB = 4, kRuleMR = 5 };
 
 struct StepParams {
   int nx, ny, nz;
@@ -36,6 +41,7 @@ struct StepParams {
   double s_zeta;      // MRT remaining kinetic modes
   double sigma;       // 16-bit storage: stored h_k = sigma * g_k / w_k
   unsigned seed;      // stochastic rounding: per-step seed
+  int wall;           // wall rule (lbm_wall) for the general wall template
 };
 
 // ------------------------------------------------------------ storage types
@@ -364,12 +370,139 @@ struct Nbr {
 // Weight class of direction k: 0 rest, 1 axis, 2 diagonal.
 __device__ __host__ constexpr int wclass(int k) { return k == 0 ? 0 : (k < 7 ? 1 : 2); }
 
+// Cell m steps from (x, y, z) along e_k, wrapped into the box; cross = +1
+// when the unwrapped x is >= nx, -1 when < 0 (the read crosses the
+// x-periodic plane and carries the density jump).
+struct FarNode {
+  int c;
+  int cross;
+};
+__device__ __forceinline__ int wrap_into(int i, int n) { return ((i % n) + n) % n; }
+__device__ __forceinline__ FarNode far_node(const StepParams& p, int x, int y, int z, int k,
+                                            int m) {
+  const int X = x + m * kLat.ex[k];
+  FarNode f;
+  f.cross = X >= p.nx ? 1 : (X < 0 ? -1 : 0);
+  f.c = wrap_into(X, p.nx) + p.nx * (wrap_into(y + m * kLat.ey[k], p.ny) +
+                                     p.ny * wrap_into(z + m * kLat.ez[k], p.nz));
+  return f;
+}
+
+// Population kk at a far node, with the jump of a crossing read.
+template <typename S, typename C>
+__device__ __forceinline__ C far_value(const S* __restrict__ src, long long st,
+                                       const StepParams& p, FarNode f, int kk) {
+  C v = (C)Storage<S>::to_float(src[kk * st + f.c]);
+  const C jw = (C)(wclass(kk) == 1 ? p.jump_axis : p.jump_diag);
+  if (f.cross > 0) v -= jw;
+  if (f.cross < 0) v += jw;
+  return v;
+}
+
+// Density deviation and velocity of the stored (post-collision) state at
+// cell c; collision conserves both, so these are the moments at time t_n.
+template <typename S, typename C>
+__device__ __forceinline__ void stored_moments(const S* __restrict__ src, long long st, int c,
+                                               C& drho, C (&u)[3]) {
+  drho = (C)0;
+  u[0] = u[1] = u[2] = (C)0;
+#pragma unroll
+  for (int kk = 0; kk < kQ; ++kk) {
+    const C v = (C)Storage<S>::to_float(src[kk * st + c]);
+    drho += v;
+    u[0] += (C)kLat.ex[kk] * v;
+    u[1] += (C)kLat.ey[kk] * v;
+    u[2] += (C)kLat.ez[kk] * v;
+  }
+}
+
+// Incoming value of direction k at fluid node (x, y, z), cell c, whose pull
+// source is solid, for the interpolated rules of Sec. 2.2.1 (eqs. (LIBB),
+// (QIBB), (fstar)-(IEBB), (MR), (CLI)) in the pull form: j = opp(k) points
+// into the wall, x_f2 = x + e_k and x_f3 = x + 2 e_k lie away from it, and
+// every right-hand side is a post-collision value of the stored state.  MR
+// uses kappa_1 = (1 - 2q - 2q^2)/(1 + q)^2 (exact for linear profiles).  A
+// rule that needs a solid node falls back: x_f2 solid -> bounce-back (LIBB
+// and QIBB with q >= 1/2 keep LIBB's q >= 1/2 branch, which needs x_f1
+// only); x_f3 solid -> LIBB (from QIBB) or CLI (from MR).  Unscaled storage
+// (FP32, FP64) only.
+template <typename S, typename C>
+__device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __restrict__ flags,
+                                const StepParams& p, int x, int y, int z, int c, int k, C q) {
+  const long long st = p.stride;
+  const int j = kLat.opp[k];
+  const C own_j = (C)Storage<S>::to_float(src[j * st + c]);
+  const C own_k = (C)Storage<S>::to_float(src[k * st + c]);
+  const FarNode n2 = far_node(p, x, y, z, k, 1);
+  const FarNode n3 = far_node(p, x, y, z, k, 2);
+  const bool f2 = !(flags[n2.c] & kSolid);
+  const bool f3 = f2 && !(flags[n3.c] & kSolid);
+  int rule = p.wall;
+  if (rule == kRuleMR && !f3) rule = kRuleCLI;
+  if (rule == kRuleQIBB && (q < (C)0.5 ? !f3 : !f2)) rule = kRuleLIBB;
+  const C one = (C)1, two = (C)2;
+  switch (rule) {
+    case kRuleCLI: {
+      if (!f2) return own_j;
+      const C a = (one - two * q) / (one + two * q);
+      return a * far_value<S, C>(src, st, p, n2, j) - a * own_k + own_j;
+    }
+    case kRuleLIBB:
+      if (q < (C)0.5) {
+        if (!f2) return own_j;
+        return (one - two * q) * far_value<S, C>(src, st, p, n2, j) + two * q * own_j;
+      }
+      return (one - one / (two * q)) * own_k + own_j / (two * q);
+    case kRuleQIBB:
+      if (q < (C)0.5)
+        return q * (one + two * q) * own_j +
+               (one - (C)4 * q * q) * far_value<S, C>(src, st, p, n2, j) -
+               q * (one - two * q) * far_value<S, C>(src, st, p, n3, j);
+      return (two * q - one) / q * own_k + own_j / (q * (two * q + one)) +
+             (one - two * q) / (two * q + one) * far_value<S, C>(src, st, p, n2, k);
+    case kRuleIEBB: {
+      C drho1, u1[3], ubf[3], X;
+      stored_moments<S, C>(src, st, c, drho1, u1);
+      const C tau = (C)(1.0 / p.omega_p);
+      if (q < (C)0.5) {
+        if (!f2) return own_j;
+        C d2;
+        stored_moments<S, C>(src, st, n2.c, d2, ubf);
+        X = (two * q - one) / (tau - two);
+      } else {
+        const C f = one - (C)3 / (two * q);
+        ubf[0] = f * u1[0];
+        ubf[1] = f * u1[1];
+        ubf[2] = f * u1[2];
+        X = (two * q - one) / (tau + (C)0.5);
+      }
+      const C eub = (C)kLat.ex[j] * ubf[0] + (C)kLat.ey[j] * ubf[1] + (C)kLat.ez[j] * ubf[2];
+      const C eu1 = (C)kLat.ex[j] * u1[0] + (C)kLat.ey[j] * u1[1] + (C)kLat.ez[j] * u1[2];
+      const C uu = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+      const C fstar =
+          (C)kLat.w[j] * (drho1 + (C)3 * eub + (C)4.5 * eu1 * eu1 - (C)1.5 * uu);
+      return (one - X) * own_j + X * fstar;
+    }
+    case kRuleMR: {
+      if (!f2) return own_j;
+      const C d = (one + q) * (one + q);
+      const C k1 = (one - two * q - two * q * q) / d, k2 = q * q / d;
+      return k1 * far_value<S, C>(src, st, p, n2, j) + k2 * far_value<S, C>(src, st, p, n3, j) -
+             k1 * own_k - k2 * far_value<S, C>(src, st, p, n2, k) + own_j;
+    }
+    default:
+      return own_j;
+  }
+}
+
+
 // One time step for the node (x, y, z), fluid, with flag word fl: pull,
 // wall rule, pressure jump, collision, store.  Returns the pre-collision
 // moments (which the collision conserves) and max_k |g*_k| / w_k of the
 // stored result, for the optional reduction.
 template <typename S, int COLL, int WALL, bool NT = false>
 __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __restrict__ dst,
+                                            const uint32_t* __restrict__ flags,
                                             const StepParams& p, int x, int y, int z, int c,
                                             uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
@@ -407,6 +540,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
 #pragma unroll
     for (int k = 1; k < kQ; ++k) {
       if (fl & (1u << k)) {
+        if constexpr (WALL == kGEN) {
+          // the pulled raw value is the link's wall distance q
+          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k]);
+          continue;
+        }
         const int j = kLat.opp[k];
         const C own_j = (C)St::to_float(src[j * st + c]) * dec[wclass(j)];
         if constexpr (WALL == kCLI) {
@@ -511,13 +649,13 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
     const uint32_t fl = flags[c];
     if (fl & kSolid) return;
     C mom[5];
-    update_node<S, COLL, WALL, NT>(src, dst, p, x, y, z, c, fl, mom);
+    update_node<S, COLL, WALL, NT>(src, dst, flags, p, x, y, z, c, fl, mom);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t fl = inside ? flags[c] : kSolid;
     if (!(fl & kSolid)) {
       C mom[5];
-      update_node<S, COLL, WALL, NT>(src, dst, p, x, y, z, c, fl, mom);
+      update_node<S, COLL, WALL, NT>(src, dst, flags, p, x, y, z, c, fl, mom);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
       v[0] = ux;
@@ -568,7 +706,7 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(
     const uint32_t fl = inside ? f[c] : kSolid;
     if (fl & kSolid) continue;
     C mom[5];
-    update_node<S, COLL, WALL, NT>(s, d, p, x, y, z, c, fl, mom);
+    update_node<S, COLL, WALL, NT>(s, d, f, p, x, y, z, c, fl, mom);
     if constexpr (RED) {
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
@@ -771,7 +909,12 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
       const int j = kLat.opp[k];
       const double own_j = stored_to_g<S>(src[j * st + c], j, p.sigma);
       double back = own_j;
-      if (WALL == kCLI) {
+      if constexpr (WALL == kGEN) {
+        const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
+                  sz = (z - kLat.ez[k] + p.nz) % p.nz;
+        const double q = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
+        back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q);
+      } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
         const double a = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);

@@ -205,13 +205,30 @@ StepParams step_params(lbm_domain d) {
   sp.s_e = d->s_e;
   sp.s_zeta = d->s_zeta;
   sp.sigma = d->sigma;
+  sp.wall = d->p.wall;
   sp.seed = hash32((uint32_t)d->step_count ^ hash32((uint32_t)(d->step_count >> 32) + 0x5bd1e995u));
   return sp;
 }
 
+// Wall template of a rule: SBB and CLI have their own, the other
+// interpolated rules share the general one (FP32/FP64 storage only).
+int wall_template(int wall) { return wall <= LBM_WALL_CLI ? wall : kGEN; }
+
+template <typename S>
+constexpr bool kUnscaled = std::is_same_v<S, float> || std::is_same_v<S, double>;
+
 template <typename S, bool RED, bool NT>
 const void* step_fn(int collision, int wall) {
-  switch (collision * 2 + wall) {
+  if constexpr (kUnscaled<S>) {
+    if (wall_template(wall) == kGEN) {
+      switch (collision) {
+        case 0: return (const void*)step_kernel<S, kSRT, kGEN, RED, NT>;
+        case 1: return (const void*)step_kernel<S, kTRT, kGEN, RED, NT>;
+        default: return (const void*)step_kernel<S, kMRT, kGEN, RED, NT>;
+      }
+    }
+  }
+  switch (collision * 2 + wall_template(wall)) {
     case 0: return (const void*)step_kernel<S, kSRT, kSBB, RED, NT>;
     case 1: return (const void*)step_kernel<S, kSRT, kCLI, RED, NT>;
     case 2: return (const void*)step_kernel<S, kTRT, kSBB, RED, NT>;
@@ -337,6 +354,13 @@ dim3 batch_grid(lbm_domain d) {
 
 template <typename S, bool RED, bool NT>
 const void* batch_fn(int collision, int wall) {
+  if (wall_template(wall) == kGEN) {
+    switch (collision) {
+      case 0: return (const void*)batch_step_kernel<S, kSRT, kGEN, RED, NT>;
+      case 1: return (const void*)batch_step_kernel<S, kTRT, kGEN, RED, NT>;
+      default: return (const void*)batch_step_kernel<S, kMRT, kGEN, RED, NT>;
+    }
+  }
   switch (collision * 2 + wall) {
     case 0: return (const void*)batch_step_kernel<S, kSRT, kSBB, RED, NT>;
     case 1: return (const void*)batch_step_kernel<S, kSRT, kCLI, RED, NT>;
@@ -515,6 +539,7 @@ lbm_status upload_cell_params(lbm_domain d) {
     sp.s_zeta = 8.0 * (2.0 - sp.omega_p) / (8.0 - sp.omega_p);
     sp.sigma = 1.0;
     sp.seed = 0;
+    sp.wall = d->p.wall;
   }
   HIP_OK(d, hipMemcpyAsync(d->d_cells, t.data(), t.size() * sizeof(StepParams),
                            hipMemcpyHostToDevice, d->stream));
@@ -691,8 +716,12 @@ LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere
   if (p.ny > 65535 || p.nz > 65535) return bad("ny and nz must be at most 65535");
   if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return bad("tau must be finite and > 1/2");
   if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
-  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_CLI) return bad("unknown wall rule");
+  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_MR) return bad("unknown wall rule");
   if (p.storage < LBM_FP64 || p.storage > LBM_BF16_RNE) return bad("unknown storage");
+  if (p.wall >= LBM_WALL_LIBB && p.storage != LBM_FP64 && p.storage != LBM_FP32)
+    return bad("LIBB, QIBB, IEBB and MR need FP32 or FP64 storage");
+  if (p.wall == LBM_WALL_IEBB && std::fabs(p.tau - 2.0) < 1e-12)
+    return bad("IEBB is undefined at tau = 2 (X = (2q-1)/(tau-2))");
   if (p.collision == LBM_TRT && !(p.magic > 0.0 && p.magic <= 0.75))
     return bad("TRT magic parameter must lie in (0, 3/4]");
   if (!std::isfinite(p.delta_rho)) return bad("delta_rho must be finite");
@@ -832,10 +861,14 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     slot[i] = (long long)kLat.opp[j] * d->stride + s;
     const double q = d->geo.link_q[i];
     // eq. (CLI): a = (1 - 2q)/(1 + 2q); links without a second fluid node
-    // fall back to simple bounce-back (a = 0)
-    coef[i] = (d->p.wall == LBM_WALL_CLI && !d->geo.link_fallback[i])
-                  ? (1.0 - 2.0 * q) / (1.0 + 2.0 * q)
-                  : 0.0;
+    // fall back to simple bounce-back (a = 0).  The other interpolated
+    // rules keep q itself and decide their fallbacks in the kernel.
+    if (d->p.wall == LBM_WALL_CLI)
+      coef[i] = d->geo.link_fallback[i] ? 0.0 : (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
+    else if (d->p.wall >= LBM_WALL_LIBB)
+      coef[i] = q;
+    else
+      coef[i] = 0.0;
   }
   if (nl) {
     HIP_OK(d, hipMemcpyAsync(d->link_slot, slot.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
@@ -1084,8 +1117,16 @@ LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   if (!F) return fail(d, LBM_ERR_INVALID_ARG, "F is NULL");
   const StepParams sp = step_params(d);
   const bool cli = d->p.wall == LBM_WALL_CLI;
+  const bool gen = wall_template(d->p.wall) == kGEN;
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
+    if constexpr (kUnscaled<S>) {
+      if (gen) {
+        drag_kernel<S, kGEN><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
+            (const S*)d->buf[d->cur], d->flags, sp, d->partials);
+        return 0;
+      }
+    }
     if (cli)
       drag_kernel<S, kCLI><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
           (const S*)d->buf[d->cur], d->flags, sp, d->partials);
@@ -1125,7 +1166,7 @@ LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
   if (p.ny > 65535 || (int64_t)p.nz * n_cells > 65535 * 64)
     return bad("ny must be at most 65535 and n_cells*nz at most 65535*64");
   if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
-  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_CLI) return bad("unknown wall rule");
+  if (p.wall < LBM_WALL_SBB || p.wall > LBM_WALL_MR) return bad("unknown wall rule");
   if (p.storage != LBM_FP64 && p.storage != LBM_FP32) return bad("batches store FP32 or FP64");
   if (p.check_interval < 0) return bad("check_interval must be >= 0");
   if ((masks != nullptr) == (spheres != nullptr)) return bad("give exactly one of masks and spheres");
@@ -1133,6 +1174,8 @@ LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
   for (int b = 0; b < n_cells; ++b) {
     const lbm_cell_params& c = cells[b];
     if (!(c.tau > 0.5) || !std::isfinite(c.tau)) return bad("cell tau must be finite and > 1/2");
+    if (p.wall == LBM_WALL_IEBB && std::fabs(c.tau - 2.0) < 1e-12)
+      return bad("IEBB is undefined at tau = 2 (X = (2q-1)/(tau-2))");
     if (p.collision == LBM_TRT && !(c.magic > 0.0 && c.magic <= 0.75))
       return bad("cell TRT magic parameter must lie in (0, 3/4]");
     if (!std::isfinite(c.delta_rho)) return bad("cell delta_rho must be finite");

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 COLLISIONS = {"srt": 0, "trt": 1, "mrt": 2}
-WALLS = {"sbb": 0, "cli": 1}
+WALLS = {"sbb": 0, "cli": 1, "libb": 2, "qibb": 3, "iebb": 4, "mr": 5}
 STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp16_rne": 4, "bf16_rne": 5}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device error", 4: "unstable",

@@ -68,7 +68,8 @@ def _create(shape=(8, 9, 10), **kw):
 
 @pytest.mark.parametrize("kw", [
     dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(magic=0.0), dict(magic=0.8),
-    dict(collision=3), dict(wall=2), dict(storage=7), dict(check_interval=-1),
+    dict(collision=3), dict(wall=6), dict(wall=-1), dict(storage=7), dict(check_interval=-1),
+    dict(wall=2, storage=2), dict(wall=5, storage=3), dict(wall=4, tau=2.0),
     dict(delta_rho=float("inf")), dict(mask=None),
 ])
 def test_invalid_arguments_are_rejected(kw):

@@ -35,19 +35,21 @@ def _oracle(orc, c, wall="cli", collision="trt"):
                       collision=collision, wall=wall, spheres=c["spheres"])
 
 
-@pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
-def test_batch_steps_match_cells(orc, collision):
+@pytest.mark.parametrize("collision,wall", [("srt", "cli"), ("trt", "cli"), ("mrt", "cli"),
+                                            ("trt", "libb"), ("trt", "qibb"), ("mrt", "iebb"),
+                                            ("trt", "mr")])
+def test_batch_steps_match_cells(orc, collision, wall):
     """Each cell of a batch evolves exactly as the same cell alone (FP64):
     per-cell parameters, z wrap inside the cell, wall coefficients."""
     cells = _cells(4, seed=1)
-    b = lbm.Batch(CELL, cells, collision=collision, wall="cli", storage="fp64")
+    b = lbm.Batch(CELL, cells, collision=collision, wall=wall, storage="fp64")
     assert np.array_equal(b.mask()[2], orc.voxelise(CELL, cells[2]["spheres"]))
     g0 = inputs.random_populations((4,) + CELL, 1e-3, seed=2)
     b.set_state(g0)
     b.step(5)
     g = b.get_state()
     for i, c in enumerate(cells):
-        o = _oracle(orc, c, collision=collision)
+        o = _oracle(orc, c, collision=collision, wall=wall)
         o.set_state(g0[:, i])
         o.step(5)
         fluid = o.mask == 0

@@ -11,7 +11,8 @@ from paper_1508_02960_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
 
-COMBOS = [(c, w) for c in ("srt", "trt", "mrt") for w in ("sbb", "cli")]
+WALLS = ("sbb", "cli", "libb", "qibb", "iebb", "mr")
+COMBOS = [(c, w) for c in ("srt", "trt", "mrt") for w in WALLS]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -119,12 +120,13 @@ def test_bench_configuration_fp32(orc):
     d.close()
 
 
+@pytest.mark.parametrize("wall", WALLS)
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_observables_parity(orc, storage, tol):
+def test_observables_parity(orc, storage, tol, wall):
     shape = (20, 18, 24)
     sp = inputs.random_spheres(shape, 4, (2.0, 4.0), seed=51)
     o, d = _pair(orc, shape, storage=storage, tau=0.9, magic=0.25, delta_rho=2e-3,
-                 collision="trt", wall="cli", spheres=sp)
+                 collision="trt", wall=wall, spheres=sp)
     u0 = inputs.random_velocity(shape, 5e-3, seed=52)
     drho0 = inputs.random_velocity(shape, 1e-3, seed=53)[0]
     o.init(drho0=drho0, u0=u0)
