@@ -101,6 +101,36 @@ def cpu_baseline(wl, budget_s: float):
                       f"{shape[0]}, {n_fluid} fluid cells), single thread, {total:.1f} s"}
 
 
+def warm_start_leg(n_cells: int):
+    """Time to steady state, plain vs learned warm start: n_cells held-out
+    random packs of 64^3 (1-4 overlapping spheres, porosity 0.35-0.6, the
+    training distribution of the stored network, a seed it was not trained
+    on), TRT-CLI FP32 at tau 0.8, each start run by the batch solver to a
+    1e-8 residual.  The warm start's time includes the network's inference."""
+    from paper_1508_02960_amd import warmstart, warmstart_study
+
+    weights = os.path.join(ROOT, "paper_1508_02960_amd", "data", "unet64_bf16.npz")
+    net = warmstart.UNet.load(weights)
+    packs = warmstart_study.draw_packs(n_cells, 64, 7, warmstart_study.TRAIN_SPHERES)
+    r = warmstart_study.evaluate(net, packs, 64, tau=0.8, delta_rho=1e-5, tol=1e-8,
+                                 max_steps=200000, controls=False,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+    plain, warm = r["rest"], r["network_u"]
+    return {
+        "workload": f"{n_cells} held-out random packs of 64^3 (1-4 spheres), TRT-CLI FP32, "
+                    "tau 0.8, residual 1e-8, one batch run per start",
+        "plain_s": round(plain["seconds"], 3),
+        "warm_s": round(warm["seconds"] + r["predict_seconds"], 3),
+        "inference_s": round(r["predict_seconds"], 3),
+        "plain_steps_median": float(np.median(plain["steps"])),
+        "warm_steps_median": float(np.median(warm["steps"])),
+        "step_ratio_median": round(warm["step_ratio_median"], 4),
+        "max_rel_K_diff": warm["max_rel_K_diff"],
+        "network_rel_error_u_median": round(float(np.median(r["network_rel_error_u"])), 4),
+        "all_converged": all(s == "converged" for s in plain["status"] + warm["status"]),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +139,8 @@ def main() -> int:
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of CPU oracle time for the cpu_baseline sample (0: skip)")
+    ap.add_argument("--warm-cells", type=int, default=16,
+                    help="held-out 64^3 packs for the plain vs warm-start comparison (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -215,6 +247,8 @@ def main() -> int:
         },
     }
     d.close()
+    if args.warm_cells > 0:
+        out["time_to_steady_state"] = warm_start_leg(args.warm_cells)
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -305,13 +305,16 @@ class UNet:
         out = self.forward(network_input(self.ctx, fluid[None].astype(np.uint8)))
         return out[0, ..., :used].float().cpu().numpy() * self.scale
 
-    def save(self, path: str) -> None:
+    def save(self, path: str, bf16: bool = False) -> None:
+        """FP32 master weights, or with bf16 the BF16 weights the kernels use
+        (as raw 16-bit patterns, compressed): inference is unchanged."""
         arrays = {"widths": np.array(self.widths), "scale": np.array(self.scale),
                   "step_count": np.array(self.step_count)}
         for i, l in enumerate(self.layers()):
-            arrays[f"w{i}"] = l.w.cpu().numpy()
+            w = l.w.cpu().numpy()
+            arrays[f"w{i}"] = _to_bf16_bits(w) if bf16 else w
             arrays[f"b{i}"] = l.b.cpu().numpy()
-        np.savez(path, **arrays)
+        (np.savez_compressed if bf16 else np.savez)(path, **arrays)
 
     @classmethod
     def load(cls, path: str, device=None) -> "UNet":
@@ -320,10 +323,20 @@ class UNet:
         net.scale = float(z["scale"])
         net.step_count = int(z["step_count"])
         for i, l in enumerate(net.layers()):
-            l.w.copy_(net.ctx.torch.from_numpy(z[f"w{i}"]))
+            w = z[f"w{i}"]
+            if w.dtype == np.uint16:
+                w = (w.astype(np.uint32) << 16).view(np.float32)
+            l.w.copy_(net.ctx.torch.from_numpy(np.ascontiguousarray(w)))
             l.b.copy_(net.ctx.torch.from_numpy(z[f"b{i}"]))
             l.refresh()
         return net
+
+
+def _to_bf16_bits(a: np.ndarray) -> np.ndarray:
+    """Round FP32 to the nearest BF16 (ties to even) as 16-bit patterns."""
+    b = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return b.astype(np.uint16)
 
 
 # ------------------------------------------------------------------ data

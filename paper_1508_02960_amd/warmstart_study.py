@@ -236,7 +236,7 @@ def _trajectory(b, start, chunk, n_chunks):
 
 def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
              device=None, log=_log, chunk: int = 0, n_chunks: int = 0,
-             with_density: bool = False):
+             with_density: bool = False, controls: bool = True):
     """Starts of the same packs, each run to tol by the plain iteration:
     rest; linear density; the network's velocity (wall layer at rest) with
     the linear density; with with_density the same plus the network's
@@ -245,7 +245,8 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
     times, the network's error against the converged fields and, with
     chunk > 0, |U_x / U_x* - 1| every chunk steps for each start.  nets is
     a network or a dict name -> network; the starts of a network named n
-    are network_u[n] and network_u_rho[n] (no suffix for a single one)."""
+    are network_u[n] and network_u_rho[n] (no suffix for a single one).
+    controls=False runs only the rest and network starts."""
     if not isinstance(nets, dict):
         nets = {"": nets}
     cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
@@ -255,7 +256,9 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
         out["launch_shape"] = list(b.autotune(steps=5)[:2])
         fluid = b.mask() == 0
         lin = W.linear_density(fluid.shape, delta_rho, fluid)
-        starts = {"rest": (None, None), "linear_density": (lin, None)}
+        starts = {"rest": (None, None)}
+        if controls:
+            starts["linear_density"] = (lin, None)
         preds = {}
         for tag, net in nets.items():
             t0 = time.perf_counter()
@@ -270,7 +273,8 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
                 starts["network_u_rho" + tag] = (np.stack([w[0] for w in wr]),
                                                  np.stack([w[1] for w in wr], axis=1))
         conv = None
-        for name, start in list(starts.items()) + [("converged_fields", None)]:
+        extra = [("converged_fields", None)] if controls else []
+        for name, start in list(starts.items()) + extra:
             if name == "converged_fields":
                 start = conv
             b.init_equilibrium(*start)
@@ -293,7 +297,8 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
                     out["network_rel_error_U" + tag] = eU
         if chunk > 0:
             Ustar = np.array(out["rest"]["U"])
-            for name in ["rest", "converged_fields"] + ["network_u" + t for t in nets]:
+            for name in ["rest"] + (["converged_fields"] if controls else []) + [
+                    "network_u" + t for t in nets]:
                 st = conv if name == "converged_fields" else starts[name]
                 traj = _trajectory(b, st, chunk, n_chunks)
                 out[name]["trajectory_rel_error"] = np.abs(traj / Ustar[None] - 1).tolist()
