@@ -58,8 +58,13 @@ lbm_status nn_conv3d_backward_weight(const void* x, const void* dy, float* dw, v
                                      size_t workspace_bytes, int n, int d, int h, int w_, int ci,
                                      int co, void* stream);
 
-/* db[c] = sum over m voxels of dy[m][c] (float). */
-lbm_status nn_bias_grad(const float* dy, float* db, long long m, int c, void* stream);
+/* Workspace bytes of nn_bias_grad for m voxels of c channels. */
+lbm_status nn_bias_grad_workspace(long long m, int c, size_t* bytes);
+
+/* db[c] = sum over m voxels of dy[m][c] (float), summed per voxel range into
+ * the workspace and folded in a fixed order (deterministic). */
+lbm_status nn_bias_grad(const float* dy, float* db, void* workspace, size_t workspace_bytes,
+                        long long m, int c, void* stream);
 
 /* a = bf16(relu ? max(z, 0) : z) for n values. */
 lbm_status nn_activation_forward(const float* z, void* a, long long n, int relu, void* stream);

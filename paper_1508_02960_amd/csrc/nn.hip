@@ -59,70 +59,133 @@ __device__ __forceinline__ long long neighbour(int n, int z, int y, int x, int t
 }
 
 // ---------------------------------------------------------------- forward
-// y[m][co] = bias[co] + sum_{tap, ci} x[m + off(tap)][ci] * w[co][tap][ci]
-// GEMM M = voxels, N = co, K = 27 ci (ci % 8 == 0).  Workgroup 256 threads
-// = 4 wavefronts; tile 64 voxels x 64 output channels; K in chunks of 32.
-// Wavefront wv computes voxel rows 16 wv .. 16 wv + 15 against the four
-// 16-channel column blocks.  MFMA operands: lane l supplies row/column
-// l % 16 and the 8 consecutive k of octet l / 16; the result holds rows
-// 4 (l / 16) + i, column l % 16.
-constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+// y[m][co] = bias[co] + sum_{tap, ci} x[m + off(tap)][ci] * w[co][tap][ci]:
+// an implicit GEMM with M = voxels, N = co and K = 27 ci (ci % 8 == 0).  MFMA
+// operands (v_mfma_f32_16x16x32_bf16): lane l supplies row/column l % 16 and
+// the 8 consecutive k of octet l / 16; the result holds rows 4 (l / 16) + i,
+// column l % 16.
+constexpr int kPad = 8;
 
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t* __restrict__ x,
-                                                       const uint16_t* __restrict__ w,
-                                                       const float* __restrict__ bias,
-                                                       float* __restrict__ y, Shape s, int ci,
-                                                       int co) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
+// Tiled forward convolution: block tile 128 voxels x BN output channels
+// (BN = 16, 32 or 64), K = 27 ci staged 64 at a time through LDS.  Each of
+// the 4 wavefronts owns 32 voxel rows (two 16-row MFMA tiles) against all
+// BN/16 column tiles.  The 27 neighbour voxels of the block's 128 rows are
+// tabulated in LDS once, so the gather of a K stage is a table lookup plus
+// the tap/channel position of the thread's 8-element granule, advanced
+// incrementally.  The next stage's global loads are issued into registers
+// before the current stage's MFMAs (one stage of prefetch).
+template <int BN>
+__global__ __launch_bounds__(256) void conv_fwd_tiled_kernel(const uint16_t* __restrict__ x,
+                                                             const uint16_t* __restrict__ w,
+                                                             const float* __restrict__ bias,
+                                                             float* __restrict__ y, Shape s,
+                                                             int ci, int co) {
+  constexpr int BM = 128, BK = 64, LD = BK + 8;
+  constexpr int NBG = BN * BK / 8;          // B granules per stage
+  constexpr int NB = (NBG + 255) / 256;     // B granules per thread (at most)
+  constexpr int NT = BN / 16;               // column tiles
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LD];
+  __shared__ int nbr[27 * BM];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const long long m0 = (long long)blockIdx.x * kBM;
-  const int n0 = blockIdx.y * kBN;
+  const long long m0 = (long long)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
   const int K = 27 * ci;
-  // this thread's load unit: row tid / 4, octet tid % 4
-  const int lr = tid >> 2, lo = tid & 3;
-  const long long lm = m0 + lr;
-  int vn = 0, vz = 0, vy = 0, vx = 0;
-  if (lm < s.m) unflatten(lm, s, vn, vz, vy, vx);
-  const int wn = n0 + lr;
-
-  f32x4 acc[4];
-  for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int k0 = 0; k0 < K; k0 += kBK) {
-    const int k = k0 + lo * 8;
-    uint4 av = make_uint4(0, 0, 0, 0), bv = make_uint4(0, 0, 0, 0);
-    if (lm < s.m && k < K) {
-      const int t = k / ci, c = k - t * ci;
-      const long long nb = neighbour(vn, vz, vy, vx, t, s);
-      av = *reinterpret_cast<const uint4*>(x + nb * ci + c);
+  for (int i = tid; i < 27 * BM; i += 256) {
+    const int t = i / BM, r = i - t * BM;
+    const long long m = m0 + r;
+    int v = -1;
+    if (m < s.m) {
+      int vn, vz, vy, vx;
+      unflatten(m, s, vn, vz, vy, vx);
+      v = (int)neighbour(vn, vz, vy, vx, t, s);
     }
-    if (wn < co && k < K) bv = *reinterpret_cast<const uint4*>(w + (long long)wn * K + k);
-    *reinterpret_cast<uint4*>(&As[lr][lo * 8]) = av;
-    *reinterpret_cast<uint4*>(&Bs[lr][lo * 8]) = bv;
-    __syncthreads();
-    const uint4 ar = *reinterpret_cast<const uint4*>(&As[wv * 16 + (lane & 15)][(lane >> 4) * 8]);
-    const bf16x8 a = __builtin_bit_cast(bf16x8, ar);
+    nbr[i] = v;
+  }
+  // this thread's granules: rows (tid >> 3) + 32 i of A, B rows from g = tid + 256 i,
+  // all at K offset koff = 8 (tid & 7) within the stage
+  const int koff = 8 * (tid & 7);
+  int ta = 0, ca = koff;
+  while (ca >= ci) {
+    ca -= ci;
+    ++ta;
+  }
+  __syncthreads();
+
+  uint4 ra[4], rb[NB];
+  auto gload = [&](int k0) {
+    const bool kin = k0 + koff < K;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      if (n0 + b * 16 < co) {
-        const uint4 br = *reinterpret_cast<const uint4*>(&Bs[b * 16 + (lane & 15)][(lane >> 4) * 8]);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, br),
-                                                         acc[b], 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      ra[i] = make_uint4(0, 0, 0, 0);
+      if (kin) {
+        const int v = nbr[ta * BM + (tid >> 3) + 32 * i];
+        if (v >= 0) ra[i] = *reinterpret_cast<const uint4*>(x + (long long)v * ci + ca);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int g = tid + 256 * i;
+      const int col = n0 + (g >> 3);
+      rb[i] = make_uint4(0, 0, 0, 0);
+      if (g < NBG && kin && col < co)
+        rb[i] = *reinterpret_cast<const uint4*>(w + (long long)col * K + k0 + koff);
+    }
+  };
+  f32x4 acc[2][NT];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<uint4*>(&As[((tid >> 3) + 32 * i) * LD + koff]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int g = tid + 256 * i;
+      if (g < NBG) *reinterpret_cast<uint4*>(&Bs[(g >> 3) * LD + koff]) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + BK < K) {
+      ca += BK;
+      while (ca >= ci) {
+        ca -= ci;
+        ++ta;
+      }
+      gload(k0 + BK);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      const int kk = ks + 8 * (lane >> 4);
+      const bf16x8 a0 = __builtin_bit_cast(
+          bf16x8, *reinterpret_cast<const uint4*>(&As[(wv * 32 + (lane & 15)) * LD + kk]));
+      const bf16x8 a1 = __builtin_bit_cast(
+          bf16x8, *reinterpret_cast<const uint4*>(&As[(wv * 32 + 16 + (lane & 15)) * LD + kk]));
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const bf16x8 bf = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&Bs[(b * 16 + (lane & 15)) * LD + kk]));
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bf, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bf, acc[1][b], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int col = n0 + b * 16 + (lane & 15);
     if (col >= co) continue;
     const float bb = bias ? bias[col] : 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long row = m0 + wv * 16 + (lane >> 4) * 4 + i;
-      if (row < s.m) y[row * co + col] = acc[b][i] + bb;
-    }
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long row = m0 + wv * 32 + r * 16 + (lane >> 4) * 4 + i;
+        if (row < s.m) y[row * co + col] = acc[r][b][i] + bb;
+      }
   }
 }
 
@@ -146,69 +209,149 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __
 // ranges: workgroup (tile of 64 co x 64 k, split s) writes its partial tile to
 // part[s][co][k]; a second kernel folds the splits in order.  MFMA A operand =
 // dy^T (co rows, m as the reduction), B operand = im2col(x) (m x k).
-constexpr int kWM = 32;  // voxels per chunk
+constexpr int kWM = 64;  // voxels per stage
 
+// Voxel coordinates advanced by `step` voxels (row-major n, z, y, x).
+__device__ __forceinline__ void advance_voxel(int& n, int& z, int& y, int& x, int step,
+                                              const Shape& s) {
+  x += step;
+  while (x >= s.w) {
+    x -= s.w;
+    if (++y == s.h) {
+      y = 0;
+      if (++z == s.d) {
+        z = 0;
+        ++n;
+      }
+    }
+  }
+}
+
+// 8 x 8 transpose of 16-bit values: in[v] holds 8 consecutive columns of
+// voxel v (dword i = columns 2i, 2i+1); out[c] holds the 8 voxels of column
+// c (dword p = voxels 2p, 2p+1).
+__device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    uint32_t o[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const uint32_t a = reinterpret_cast<const uint32_t*>(&in[2 * p])[c >> 1];
+      const uint32_t b = reinterpret_cast<const uint32_t*>(&in[2 * p + 1])[c >> 1];
+      o[p] = (c & 1) ? ((a >> 16) | (b & 0xFFFF0000u)) : ((a & 0xFFFFu) | (b << 16));
+    }
+    out[c] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// Weight gradient tile: TM output channels (32 or 64) x 64 im2col columns,
+// reduced over a split's voxels in stages of 64.  A stage of each operand is
+// cut into 8-column x 8-voxel blocks; thread t < TM loads dy block t, thread
+// TM <= t < TM + 64 loads x block t - TM (8 gathered 16-byte loads, one per
+// voxel: the 8 columns share one tap), transposes it in registers and writes
+// 8 rows of 16 bytes to LDS ([column][voxel]), the layout the MFMA reduction
+// over voxels needs.  With TM = 64 wavefront wv computes rows 16 wv..+15
+// against four 16-column tiles; with TM = 32 it computes rows 16 (wv % 2)
+// against tiles 2 (wv / 2), +1.  One stage of register prefetch.
+template <int TM>
 __global__ __launch_bounds__(256) void conv_bwdw_kernel(const uint16_t* __restrict__ x,
                                                         const uint16_t* __restrict__ dy,
                                                         float* __restrict__ part, Shape s, int ci,
                                                         int co, long long chunks_per_split) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ds[64][kWM + kPad];  // [co][m]
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[64][kWM + kPad];  // [k][m]
+  constexpr int LDW = kWM + kPad;
+  __shared__ __attribute__((aligned(16))) uint16_t Ds[TM][LDW];  // [co][m]
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[64][LDW];  // [k][m]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = 27 * ci;
-  const int c0 = blockIdx.x * 64;   // co tile
+  const int c0 = blockIdx.x * TM;   // co tile
   const int kt0 = blockIdx.y * 64;  // k tile
-  const int split = blockIdx.z;
-  const long long mbeg = (long long)split * chunks_per_split * kWM;
+  const long long mbeg = (long long)blockIdx.z * chunks_per_split * kWM;
   const long long mend = std::min<long long>(s.m, mbeg + chunks_per_split * kWM);
-  f32x4 acc[4];
-  for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // load units: dy tile 32 m x 64 co = 256 octets (m = tid / 8, co octet tid % 8)
-  //             x tile  32 m x 64 k  = 256 octets (m = tid / 8, k octet tid % 8)
-  const int um = tid >> 3, uo = tid & 7;
+
+  // this thread's block: columns 8 cb .. 8 cb + 7 of dy (is_dy) or of im2col(x),
+  // voxels 8 vb .. 8 vb + 7 of the stage
+  const bool is_dy = tid < TM;
+  const bool has_block = tid < TM + 64;
+  const int blk = is_dy ? tid : tid - TM;
+  const int cb = blk >> 3, vb = blk & 7;
+  const int col = is_dy ? c0 + 8 * cb : kt0 + 8 * cb;
+  const bool col_ok = has_block && (is_dy ? col < co : col < K);
+  const int tap = (!is_dy && col_ok) ? col / ci : 0;
+  const int ch = is_dy ? 0 : col - tap * ci;
+  const int dz = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dxo = tap % 3 - 1;
+  int vn = 0, vz = 0, vy = 0, vx = 0;  // coordinates of the block's first voxel
+  {
+    const long long m = mbeg + 8 * vb;
+    if (m < s.m) unflatten(m, s, vn, vz, vy, vx);
+  }
+  uint4 raw[8];
+  auto gload = [&](long long mc) {
+    int n = vn, z = vz, y = vy, xx = vx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long long m = mc + 8 * vb + j;
+      raw[j] = make_uint4(0, 0, 0, 0);
+      if (col_ok && m < mend) {
+        if (is_dy) {
+          raw[j] = *reinterpret_cast<const uint4*>(dy + m * co + col);
+        } else {
+          int zz = z + dz, yy = y + dyo, xq = xx + dxo;
+          zz = zz < 0 ? zz + s.d : (zz >= s.d ? zz - s.d : zz);
+          yy = yy < 0 ? yy + s.h : (yy >= s.h ? yy - s.h : yy);
+          xq = xq < 0 ? xq + s.w : (xq >= s.w ? xq - s.w : xq);
+          const long long v = (((long long)n * s.d + zz) * s.h + yy) * s.w + xq;
+          raw[j] = *reinterpret_cast<const uint4*>(x + v * ci + ch);
+        }
+      }
+      advance_voxel(n, z, y, xx, 1, s);
+    }
+  };
+  constexpr int NT = TM == 64 ? 4 : 2;  // column tiles per wavefront
+  const int row0 = TM == 64 ? 16 * wv : 16 * (wv & 1);
+  const int tile0 = TM == 64 ? 0 : 2 * (wv >> 1);
+  f32x4 acc[NT];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (has_block) gload(mbeg);
   for (long long mc = mbeg; mc < mend; mc += kWM) {
-    const long long m = mc + um;
-    uint4 dv = make_uint4(0, 0, 0, 0), xv = make_uint4(0, 0, 0, 0);
-    if (m < mend) {
-      const int cc = c0 + uo * 8;
-      if (cc < co) dv = *reinterpret_cast<const uint4*>(dy + m * co + cc);
-      const int k = kt0 + uo * 8;
-      if (k < K) {
-        int vn, vz, vy, vx;
-        unflatten(m, s, vn, vz, vy, vx);
-        const int t = k / ci, c = k - t * ci;
-        xv = *reinterpret_cast<const uint4*>(x + neighbour(vn, vz, vy, vx, t, s) * ci + c);
+    if (has_block) {
+      uint4 tr[8];
+      transpose8x8(raw, tr);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        uint16_t* dst = is_dy ? &Ds[8 * cb + e][8 * vb] : &Xs[8 * cb + e][8 * vb];
+        *reinterpret_cast<uint4*>(dst) = tr[e];
       }
     }
-    // transpose into LDS: element e of the octet goes to row (octet*8 + e), column um
-    const uint16_t* dp = reinterpret_cast<const uint16_t*>(&dv);
-    const uint16_t* xp = reinterpret_cast<const uint16_t*>(&xv);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      Ds[uo * 8 + e][um] = dp[e];
-      Xs[uo * 8 + e][um] = xp[e];
-    }
     __syncthreads();
-    if (c0 + wv * 16 < co) {
-      const uint4 ar = *reinterpret_cast<const uint4*>(&Ds[wv * 16 + (lane & 15)][(lane >> 4) * 8]);
-      const bf16x8 a = __builtin_bit_cast(bf16x8, ar);
+    if (has_block && mc + kWM < mend) {
+      advance_voxel(vn, vz, vy, vx, kWM, s);
+      gload(mc + kWM);
+    }
+    if (c0 + row0 < co) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const uint4 br = *reinterpret_cast<const uint4*>(&Xs[b * 16 + (lane & 15)][(lane >> 4) * 8]);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, br),
-                                                         acc[b], 0, 0, 0);
+      for (int ks = 0; ks < kWM; ks += 32) {
+        const int kk = ks + 8 * (lane >> 4);
+        const bf16x8 a = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&Ds[row0 + (lane & 15)][kk]));
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+          const bf16x8 bf = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(&Xs[(tile0 + b) * 16 + (lane & 15)][kk]));
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf, acc[b], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
-  float* out = part + (long long)split * co * K;
+  float* out = part + (long long)blockIdx.z * co * K;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int k = kt0 + b * 16 + (lane & 15);
+  for (int b = 0; b < NT; ++b) {
+    const int k = kt0 + (tile0 + b) * 16 + (lane & 15);
     if (k >= K) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int o = c0 + wv * 16 + (lane >> 4) * 4 + i;
+      const int o = c0 + row0 + (lane >> 4) * 4 + i;
       if (o < co) out[(long long)o * K + k] = acc[b][i];
     }
   }
@@ -224,22 +367,43 @@ __global__ void fold_splits_kernel(const float* __restrict__ part, float* __rest
   }
 }
 
-// db[c] = sum_m dy[m][c] (fixed order per channel, block per channel)
-__global__ __launch_bounds__(256) void bias_grad_kernel(const float* __restrict__ dy,
-                                                        float* __restrict__ db, long long m,
-                                                        int c) {
+// db[c] = sum_m dy[m][c], first pass: block b sums voxels [b per, (b+1) per)
+// into part[b][c].  Thread (g, ch) of the G = 256 / c groups handles
+// channel ch (consecutive threads read consecutive channels of a voxel) and
+// voxels g, g + G, ...; the groups are folded in a fixed order in LDS, and
+// fold_splits_kernel sums the blocks in order (deterministic).
+__global__ __launch_bounds__(256) void bias_grad_part_kernel(const float* __restrict__ dy,
+                                                             float* __restrict__ part,
+                                                             long long m, int c,
+                                                             long long per) {
   __shared__ float sh[256];
-  const int ch = blockIdx.x;
-  float a = 0.f;
-  for (long long i = threadIdx.x; i < m; i += 256) a += dy[i * c + ch];
-  sh[threadIdx.x] = a;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+  const int G = c <= 256 ? 256 / c : 1;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < m ? beg + per : m;
+  for (int cb = 0; cb < c; cb += 256) {
+    const int tid = threadIdx.x;
+    const int g = c <= 256 ? tid / c : 0;
+    const int ch = c <= 256 ? tid % c : cb + tid;
+    float a = 0.f;
+    if (g < G && ch < c)
+      for (long long v = beg + g; v < end; v += G) a += dy[v * c + ch];
+    sh[tid] = a;
     __syncthreads();
+    if (c <= 256) {
+      if (tid < c) {
+        float t = 0.f;
+        for (int q = 0; q < G; ++q) t += sh[q * c + tid];
+        part[(long long)blockIdx.x * c + tid] = t;
+      }
+    } else if (ch < c) {
+      part[(long long)blockIdx.x * c + ch] = a;
+    }
+    __syncthreads();
+    if (c <= 256) break;
   }
-  if (threadIdx.x == 0) db[ch] = sh[0];
 }
+
+constexpr int kBiasSplits = 512;
 
 // --------------------------------------------------------------- elementwise
 
@@ -443,9 +607,18 @@ NN_API lbm_status nn_conv3d_forward(const void* x, const void* w, const float* b
   if (!x || !w || !y || bad_shape(n, d, h, wd) || ci < 8 || ci % 8 || co < 1)
     return LBM_ERR_INVALID_ARG;
   const Shape s = shape_of(n, d, h, wd);
-  dim3 grid((unsigned)((s.m + kBM - 1) / kBM), (unsigned)((co + kBN - 1) / kBN));
-  conv_fwd_kernel<<<grid, 256, 0, (hipStream_t)stream>>>((const uint16_t*)x, (const uint16_t*)w,
-                                                         bias, y, s, ci, co);
+  if (s.m >= (1LL << 31)) return LBM_ERR_INVALID_ARG;  // voxel indices are 32-bit in the tables
+  const int bn = co <= 16 ? 16 : (co <= 32 ? 32 : 64);
+  dim3 grid((unsigned)((s.m + 127) / 128), (unsigned)((co + bn - 1) / bn));
+  const hipStream_t st = (hipStream_t)stream;
+  const uint16_t* xx = (const uint16_t*)x;
+  const uint16_t* ww = (const uint16_t*)w;
+  if (bn == 16)
+    conv_fwd_tiled_kernel<16><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+  else if (bn == 32)
+    conv_fwd_tiled_kernel<32><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+  else
+    conv_fwd_tiled_kernel<64><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
   return check_launch();
 }
 
@@ -467,7 +640,8 @@ NN_API lbm_status nn_conv3d_backward_weight_workspace(int n, int d, int h, int w
   if (!bytes || bad_shape(n, d, h, wd) || ci < 8 || ci % 8 || co < 8 || co % 8)
     return LBM_ERR_INVALID_ARG;
   const long long m = (long long)n * d * h * wd;
-  const long long tiles = (long long)((co + 63) / 64) * ((27 * ci + 63) / 64);
+  const int tm = co <= 32 ? 32 : 64;
+  const long long tiles = (long long)((co + tm - 1) / tm) * ((27 * ci + 63) / 64);
   const long long chunks = (m + kWM - 1) / kWM;
   long long sp = std::max<long long>(1, std::min<long long>(chunks, 2048 / std::max<long long>(tiles, 1)));
   sp = std::min<long long>(sp, 256);
@@ -487,17 +661,38 @@ NN_API lbm_status nn_conv3d_backward_weight(const void* x, const void* dy, float
   const Shape s = shape_of(n, d, h, wd);
   const long long chunks = (s.m + kWM - 1) / kWM;
   const long long per = (chunks + sp - 1) / sp;
-  dim3 grid((unsigned)((co + 63) / 64), (unsigned)((27 * ci + 63) / 64), (unsigned)sp);
-  conv_bwdw_kernel<<<grid, 256, 0, (hipStream_t)stream>>>((const uint16_t*)x, (const uint16_t*)dy,
-                                                          (float*)ws, s, ci, co, per);
+  const int tm = co <= 32 ? 32 : 64;
+  dim3 grid((unsigned)((co + tm - 1) / tm), (unsigned)((27 * ci + 63) / 64), (unsigned)sp);
+  if (tm == 32)
+    conv_bwdw_kernel<32><<<grid, 256, 0, (hipStream_t)stream>>>(
+        (const uint16_t*)x, (const uint16_t*)dy, (float*)ws, s, ci, co, per);
+  else
+    conv_bwdw_kernel<64><<<grid, 256, 0, (hipStream_t)stream>>>(
+        (const uint16_t*)x, (const uint16_t*)dy, (float*)ws, s, ci, co, per);
   const long long nw = (long long)co * 27 * ci;
   fold_splits_kernel<<<grid_for(nw), 256, 0, (hipStream_t)stream>>>((const float*)ws, dw, nw, sp);
   return check_launch();
 }
 
-NN_API lbm_status nn_bias_grad(const float* dy, float* db, long long m, int c, void* stream) {
-  if (!dy || !db || m < 1 || c < 1) return LBM_ERR_INVALID_ARG;
-  bias_grad_kernel<<<c, 256, 0, (hipStream_t)stream>>>(dy, db, m, c);
+NN_API lbm_status nn_bias_grad_workspace(long long m, int c, size_t* bytes) {
+  if (!bytes || m < 1 || c < 1) return LBM_ERR_INVALID_ARG;
+  const long long splits = std::min<long long>(kBiasSplits, (m + 255) / 256);
+  *bytes = (size_t)splits * c * sizeof(float);
+  return LBM_OK;
+}
+
+NN_API lbm_status nn_bias_grad(const float* dy, float* db, void* ws, size_t ws_bytes, long long m,
+                               int c, void* stream) {
+  size_t need = 0;
+  lbm_status st = nn_bias_grad_workspace(m, c, &need);
+  if (st != LBM_OK || !dy || !db) return LBM_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < need) return LBM_ERR_WORKSPACE;
+  const long long splits = need / ((size_t)c * sizeof(float));
+  const long long per = (m + splits - 1) / splits;
+  bias_grad_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(dy, (float*)ws, m, c,
+                                                                          per);
+  fold_splits_kernel<<<grid_for(c), 256, 0, (hipStream_t)stream>>>((const float*)ws, db, c,
+                                                                  (int)splits);
   return check_launch();
 }
 

@@ -44,7 +44,8 @@ def _nn():
         "nn_conv3d_backward_weight_workspace": [i32, i32, i32, i32, i32, i32, C.POINTER(sz),
                                                 C.POINTER(i32)],
         "nn_conv3d_backward_weight": [vp, vp, vp, vp, sz, i32, i32, i32, i32, i32, i32, vp],
-        "nn_bias_grad": [vp, vp, i64, i32, vp],
+        "nn_bias_grad_workspace": [i64, i32, C.POINTER(sz)],
+        "nn_bias_grad": [vp, vp, vp, sz, i64, i32, vp],
         "nn_activation_forward": [vp, vp, i64, i32, vp],
         "nn_relu_backward": [vp, vp, vp, i64, vp],
         "nn_cast_bf16": [vp, vp, i64, vp],
@@ -69,6 +70,7 @@ def _nn():
 NN_EXPORTS = (
     "nn_conv3d_forward", "nn_conv3d_flip_weights", "nn_conv3d_backward_data",
     "nn_conv3d_backward_weight_workspace", "nn_conv3d_backward_weight", "nn_bias_grad",
+    "nn_bias_grad_workspace",
     "nn_activation_forward", "nn_relu_backward", "nn_cast_bf16", "nn_pool2_forward",
     "nn_pool2_backward", "nn_upsample2_forward", "nn_upsample2_backward", "nn_concat_channels",
     "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam",
@@ -152,7 +154,11 @@ class Conv:
         _chk(lib.nn_conv3d_backward_weight(_p(x_bf), _p(dy), _p(self.gw), _p(ws), nbytes.value,
                                            n, d, h, w, self.ci, self.co, self.ctx.stream),
              "conv backward weight")
-        _chk(lib.nn_bias_grad(_p(dy32), _p(self.gb), m, self.co, self.ctx.stream), "bias grad")
+        bb = C.c_size_t()
+        _chk(lib.nn_bias_grad_workspace(m, self.co, C.byref(bb)), "bias ws")
+        bws = self.ctx.torch.empty(int(bb.value), dtype=self.ctx.torch.uint8, device=self.ctx.dev)
+        _chk(lib.nn_bias_grad(_p(dy32), _p(self.gb), _p(bws), bb.value, m, self.co,
+                              self.ctx.stream), "bias grad")
         if not need_dx:
             return None
         dx = self.ctx.f32(n, d, h, w, self.ci)

@@ -358,11 +358,18 @@ def main(argv=None) -> int:
     ev.add_argument("--chunk", type=int, default=0)
     ev.add_argument("--n-chunks", type=int, default=0)
     ev.add_argument("--out", required=True)
+    sp = sub.add_parser("speed")
+    sp.add_argument("--edge", type=int, default=64)
+    sp.add_argument("--minibatch", type=int, default=4)
+    sp.add_argument("--steps", type=int, default=10)
     rp = sub.add_parser("report")
     rp.add_argument("--train", nargs="*", default=[], help="title=history.json")
     rp.add_argument("--eval", nargs="*", default=[], help="title=eval.json")
     rp.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "speed":
+        speed(a.edge, a.minibatch, a.steps)
+        return 0
     if a.cmd == "report":
         parts = []
         for item in a.train:
@@ -410,6 +417,71 @@ def main(argv=None) -> int:
                  f"max |K/K_rest - 1| {res[name]['max_rel_K_diff']:.2e}")
     return 0
 
+
+
+# ------------------------------------------------------------------ speed
+
+def conv_flops(net, shape) -> float:
+    """Multiply-add flops of one forward pass over (n, d, h, w) voxels:
+    2 * 27 * c_in * c_out per output voxel of each convolution."""
+    n, d, h, w = shape
+    tot = 0.0
+    levels = {id(c): l for l, c in enumerate(net.enc)}
+    levels.update({id(c): 2 - j for j, c in enumerate(net.dec)})
+    levels[id(net.head)] = 0
+    for c in net.layers():
+        m = n * (d >> levels[id(c)]) * (h >> levels[id(c)]) * (w >> levels[id(c)])
+        tot += 2.0 * 27 * c.ci * c.co * m
+    return tot
+
+
+def speed(edge: int = 64, minibatch: int = 4, steps: int = 10, widths=(32, 64, 128, 256),
+          log=_log):
+    """Time forward and forward + backward + Adam training steps of the
+    network on random masks (HIP events on torch's stream)."""
+    import torch
+
+    net = W.UNet(widths=widths, seed=0)
+    rng = np.random.default_rng(0)
+    fluid = (rng.uniform(size=(minibatch, edge, edge, edge)) > 0.4).astype(np.uint8)
+    x = W.network_input(net.ctx, fluid)
+    tgt = torch.zeros((minibatch, edge, edge, edge, 4), device=net.ctx.dev)
+    wt = torch.from_numpy(fluid.astype(np.float32)).to(net.ctx.dev)
+    norm = 4.0 * float(fluid.sum())
+
+    def train_step():
+        out = net.forward(x)
+        _, g = net.loss(out, tgt, wt, norm, sync=False)
+        net.backward(g)
+        net.adam_step(1e-4)
+
+    for _ in range(2):
+        train_step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.forward(x)
+    e1.record()
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / steps
+    e0.record()
+    for _ in range(steps):
+        train_step()
+    e1.record()
+    e1.synchronize()
+    train_ms = e0.elapsed_time(e1) / steps
+    f = conv_flops(net, (minibatch, edge, edge, edge))
+    # backward: data gradient of every layer but the first, and weight gradients
+    first = 2.0 * 27 * net.enc[0].ci * net.enc[0].co * minibatch * edge ** 3
+    ftrain = 3 * f - first
+    res = dict(edge=edge, minibatch=minibatch, params=net.n_params(), forward_ms=fwd_ms,
+               train_ms=train_ms, forward_tflops=f / fwd_ms / 1e9,
+               train_tflops=ftrain / train_ms / 1e9, forward_gflop=f / 1e9,
+               train_gflop=ftrain / 1e9)
+    log(f"[speed] {edge}^3 x {minibatch}: forward {fwd_ms:.2f} ms ({res['forward_tflops']:.1f} "
+        f"TFLOP/s), train step {train_ms:.2f} ms ({res['train_tflops']:.1f} TFLOP/s)")
+    return res
 
 
 # ----------------------------------------------------------------- report

@@ -78,8 +78,11 @@ def test_conv_forward_backward_match_reference(ctx, shape, ci, co):
                                              nb.value, n, d, h, wd, ci, co, ctx.stream) == 0
         assert rel(_host(dw), dw_ref) < 1e-5
         db = ctx.f32(co)
-        assert lib.nn_bias_grad(W._p(_f_dev(ctx, dy)), W._p(db), n * d * h * wd, co,
-                                ctx.stream) == 0
+        bb = C.c_size_t()
+        assert lib.nn_bias_grad_workspace(n * d * h * wd, co, C.byref(bb)) == 0
+        bws = ctx.torch.empty(bb.value, dtype=ctx.torch.uint8, device=ctx.dev)
+        assert lib.nn_bias_grad(W._p(_f_dev(ctx, dy)), W._p(db), W._p(bws), bb.value,
+                                n * d * h * wd, co, ctx.stream) == 0
         assert rel(_host(db), db_ref) < 1e-5
 
 
