@@ -120,3 +120,32 @@ def test_batch_autotune_and_unstable_cell():
     assert r["status"][1] == "unstable"
     assert r["status"][0] == "converged" and r["status"][2] == "converged"
     b.close()
+
+
+def test_full_batch_configuration_sampled_cells(orc):
+    """The full 256-cell batch of 64^3 cells (one sphere of D in [40, 60] at a
+    random centre, tau in [0.55, 1], seed 4, as the batch study draws them),
+    FP32, autotuned launch shape, 40 steps from rest under per-cell pressure
+    drops; sampled cells (first, middle, last) against the FP64 oracle run on
+    that cell alone: velocity within 1e-5."""
+    from paper_1508_02960_amd import batch_study
+
+    draws, _ = batch_study.draw_cells(256, 4, 64)
+    cells = [dict(spheres=c["spheres"], tau=c["tau"], magic=3 / 16,
+                  delta_rho=1e-4 * (1 + (i % 7))) for i, c in enumerate(draws)]
+    b = lbm.Batch((64, 64, 64), cells, wall="cli", storage="fp32")
+    b.autotune(steps=3)
+    b.init_equilibrium()
+    b.step(40)
+    _, u = b.macroscopic()
+    b.close()
+    for i in (0, 127, 255):
+        c = cells[i]
+        o = orc.Oracle((64, 64, 64), tau=c["tau"], magic=c["magic"], delta_rho=c["delta_rho"],
+                       collision="trt", wall="cli", spheres=c["spheres"])
+        o.init()
+        o.step(40)
+        _, uo = o.macroscopic()
+        fluid = o.mask == 0
+        err = np.max(np.abs(u[:, i][:, fluid] - uo[:, fluid])) / np.max(np.abs(uo[:, fluid]))
+        assert err < 1e-5, (i, err)

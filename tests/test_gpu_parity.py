@@ -315,3 +315,33 @@ def test_forchheimer_sweep_matches_oracle(orc):
     assert abs(res["K_D"] / K - 1) < 1e-7
     assert abs(res["beta"] / beta - 1) < 1e-5
     assert res["beta"] > 0
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16_rne"])
+def test_largest_configuration_matches_its_quarter(storage):
+    """The 512^3 configuration (2 x 2 x 2 cells of 256^3, sphere D = 240 per
+    cell, TRT Lambda = 6e-6, tau = 0.5005, CLI) holds 19 x 1.3e8 values per
+    buffer, beyond 32-bit element offsets.  Started from rest, its flow is
+    periodic with period 256 in y and z, so every y/z quarter must equal,
+    bit for bit, the 512 x 256 x 256 box with the two spheres along x, whose
+    offsets stay below 2^31 (and whose arithmetic the 128^3 parity test
+    pins to the oracle).  16-bit storage rounds to nearest here: stochastic
+    rounding draws from the cell index, which differs between the boxes."""
+    from paper_1508_02960_amd import inputs as I
+
+    kw = dict(tau=0.5005, magic=6e-6, delta_rho=1e-5, collision="trt", wall="cli",
+              storage=storage)
+    big = lbm.Domain((512, 512, 512), spheres=I.simple_cubic_array(2, 256, 240.0), **kw)
+    small_sp = np.array([[127.5, 127.5, 127.5, 120.0], [383.5, 127.5, 127.5, 120.0]])
+    small = lbm.Domain((256, 256, 512), spheres=small_sp, **kw)
+    for d in (big, small):
+        d.init_equilibrium()
+        d.step(12)
+    _, ub = big.macroscopic()
+    _, us = small.macroscopic()
+    big.close()
+    small.close()
+    assert np.abs(us).max() > 0
+    for zq in (0, 256):
+        for yq in (0, 256):
+            assert np.array_equal(ub[:, zq:zq + 256, yq:yq + 256, :], us), (zq, yq)
