@@ -69,11 +69,11 @@ def _save(path, res):
 
 
 def grid_study(sizes=(8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128), tau=0.8,
-               magic=0.25, log=print, out=None):
+               magic=0.25, log=print, out=None, collisions=COLLISIONS):
     res = dict(chi=CHI, tau=tau, magic=magic, rows=[])
     rows = res["rows"]
     for L in sizes:
-        for coll in COLLISIONS:
+        for coll in collisions:
             t0 = time.perf_counter()
             for wall in WALLS:
                 r = run_sphere(L, radius_for(L), collision=coll, wall=wall, tau=tau, magic=magic)
@@ -161,6 +161,7 @@ def main(argv=None) -> int:
     sub = ap.add_subparsers(dest="cmd", required=True)
     g = sub.add_parser("grid")
     g.add_argument("--sizes", default="8,10,12,14,16,20,24,28,32,40,48,64,96,128")
+    g.add_argument("--collisions", default="srt,trt,mrt")
     g.add_argument("--out", required=True)
     v = sub.add_parser("viscosity")
     v.add_argument("--out", required=True)
@@ -170,7 +171,8 @@ def main(argv=None) -> int:
     r.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "grid":
-        grid_study(tuple(int(s) for s in a.sizes.split(",")), out=a.out)
+        grid_study(tuple(int(s) for s in a.sizes.split(",")), out=a.out,
+                   collisions=tuple(a.collisions.split(",")))
     elif a.cmd == "viscosity":
         viscosity_study(out=a.out)
     else:
