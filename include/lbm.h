@@ -195,6 +195,18 @@ lbm_status lbm_run_to_residual(lbm_domain d, double tol, int64_t max_steps,
  * Either pointer may be NULL. */
 lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u);
 
+/* The same fields in device memory, without a host round trip (e.g. as
+ * training targets): fields is a caller-owned device double[4*ncell] laid out
+ * as [drho | u_x | u_y | u_z], each block ncell values in cell order.
+ * Asynchronous on the domain's stream. */
+lbm_status lbm_macroscopic_device(lbm_domain d, double* fields);
+
+/* lbm_init_equilibrium from device fields in the layout of
+ * lbm_macroscopic_device (e.g. a predicted warm start).  FP32 and FP64
+ * storage only (LBM_ERR_INVALID_ARG otherwise: 16-bit storage picks its
+ * scale from the host fields).  Asynchronous on the domain's stream. */
+lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* fields);
+
 /* Superficial mean velocity U[3] = sum over fluid cells of u / ncell, the
  * largest |u| over fluid cells and the total density deviation, reduced in
  * double precision on the device.  Any pointer may be NULL. */

@@ -1075,6 +1075,41 @@ LBM_API lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u) {
   return LBM_OK;
 }
 
+LBM_API lbm_status lbm_macroscopic_device(lbm_domain d, double* fields) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!fields) return fail(d, LBM_ERR_INVALID_ARG, "fields is NULL");
+  const int n = (int)d->geo.ncell;
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    macro_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
+        (const S*)d->buf[d->cur], d->flags, d->stride, d->sigma, 0, n, fields);
+    return 0;
+  });
+  HIP_OK(d, hipGetLastError());
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* fields) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (!fields) return fail(d, LBM_ERR_INVALID_ARG, "fields is NULL");
+  if (d->p.storage != LBM_FP32 && d->p.storage != LBM_FP64)
+    return fail(d, LBM_ERR_INVALID_ARG,
+                "device initialisation needs FP32 or FP64 storage (16-bit storage chooses its "
+                "scale from the host fields)");
+  const int n = (int)d->geo.ncell;
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    init_eq_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
+        (S*)d->buf[d->cur], d->flags, d->stride, d->sigma, 0, n, fields);
+    return 0;
+  });
+  HIP_OK(d, hipGetLastError());
+  d->unstable = false;
+  return LBM_OK;
+}
+
 LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
                                      double* total_drho) {
   lbm_status st = check_ready(d);

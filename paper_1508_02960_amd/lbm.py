@@ -27,7 +27,7 @@ EXPORTS = (
     "lbm_run_to_residual", "lbm_macroscopic", "lbm_mean_velocity", "lbm_permeability",
     "lbm_drag", "lbm_set_delta_rho", "lbm_synchronize", "lbm_destroy", "lbm_status_string",
     "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
-    "lbm_batch_autotune",
+    "lbm_batch_autotune", "lbm_macroscopic_device", "lbm_init_equilibrium_device",
 )
 
 
@@ -96,6 +96,8 @@ def library():
         "lbm_step": [vp, i64],
         "lbm_run_to_residual": [vp, d, i64, P(i64), P(d)],
         "lbm_macroscopic": [vp, vp, vp],
+        "lbm_macroscopic_device": [vp, vp],
+        "lbm_init_equilibrium_device": [vp, vp],
         "lbm_mean_velocity": [vp, vp, P(d), P(d)],
         "lbm_permeability": [vp, P(d), P(d)],
         "lbm_drag": [vp, vp],
@@ -281,6 +283,22 @@ class Domain:
         u = np.zeros((3,) + self.shape)
         self._check(library().lbm_macroscopic(self._h, _ptr(drho), _ptr(u)))
         return drho, u
+
+    def macroscopic_device(self):
+        """(4, ncell) float64 tensor on the domain's device: drho, u_x, u_y,
+        u_z in cell order (no host round trip)."""
+        import torch
+
+        out = torch.empty((4, self.ncell), dtype=torch.float64, device=self._ws.device)
+        self._check(library().lbm_macroscopic_device(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def init_equilibrium_device(self, fields) -> None:
+        """Equilibrium of device fields (4, ncell) float64 laid out as from
+        macroscopic_device (FP32 and FP64 storage)."""
+        if tuple(fields.shape) != (4, self.ncell) or not fields.is_contiguous():
+            raise ValueError("fields must be a contiguous (4, ncell) tensor")
+        self._check(library().lbm_init_equilibrium_device(self._h, C.c_void_p(fields.data_ptr())))
 
     def mean_velocity(self):
         U = np.zeros(3)

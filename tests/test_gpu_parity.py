@@ -345,3 +345,35 @@ def test_largest_configuration_matches_its_quarter(storage):
     for zq in (0, 256):
         for yq in (0, 256):
             assert np.array_equal(ub[:, zq:zq + 256, yq:yq + 256, :], us), (zq, yq)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_device_fields_match_host(storage):
+    """lbm_macroscopic_device gives the host fields bit for bit, and
+    lbm_init_equilibrium_device sets the same state as the host call."""
+    import torch
+
+    shape = (10, 12, 14)
+    sp = inputs.random_spheres(shape, 3, (1.5, 3.0), seed=71)
+    u0 = inputs.random_velocity(shape, 1e-3, seed=72)
+    r0 = inputs.random_velocity(shape, 1e-4, seed=73)[0]
+    kw = dict(tau=0.8, delta_rho=1e-3, wall="cli", storage=storage, spheres=sp)
+    a = lbm.Domain(shape, **kw)
+    a.init_equilibrium(drho0=r0, u0=u0)
+    a.step(5)
+    dr, u = a.macroscopic()
+    dev = a.macroscopic_device()
+    torch.cuda.synchronize()
+    host = dev.cpu().numpy()
+    assert np.array_equal(host[0], dr.ravel()) and np.array_equal(host[1:], u.reshape(3, -1))
+    b = lbm.Domain(shape, **kw)
+    f = torch.from_numpy(np.concatenate([r0.ravel()[None], u0.reshape(3, -1)])).cuda()
+    b.init_equilibrium_device(f)
+    a.init_equilibrium(drho0=r0, u0=u0)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+    c = lbm.Domain(shape, **dict(kw, storage="fp16"))
+    with pytest.raises(lbm.LbmError):
+        c.init_equilibrium_device(f)
+    c.close()
