@@ -550,10 +550,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S* __rest
         if constexpr (WALL == kCLI) {
           const C a = g[k];
           const C own_k = (C)St::to_float(src[k * st + c]) * dec[wclass(k)];
-          // second node x_f2 = x + e_k (away from the wall), read across the
-          // x-periodic plane with the pressure jump
-          C far_j = (C)St::to_float(src[j * st + n.at(kLat.ex[k], kLat.ey[k], kLat.ez[k])]) *
-                    dec[wclass(j)];
+          // g_j at the second node x_f2 = x + e_k (away from the wall) is what
+          // this node pulls in direction j, so g[j] already holds it (raw); it
+          // is read across the x-periodic plane with the pressure jump.  If
+          // x_f2 is solid, g[j] is a coefficient and a = 0.
+          C far_j = g[j] * dec[wclass(j)];
           if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
           if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
           g[k] = a * far_j - a * own_k + own_j;
