@@ -265,12 +265,26 @@ lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64_t* step
  * per workgroup (zper, a divisor of nz). */
 lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper);
 
-/* Time every admissible (by, zper) over `steps` steps each (after two
- * warm-up steps) with HIP events on the domain's stream, keep the fastest,
- * and return it with its time per step in ms.  The state is reset to rest
- * afterwards. */
+/* Time every admissible (by, zper) and solid-write mode (lbm_set_solid_writes)
+ * over `steps` steps each (after two warm-up steps) with HIP events on the
+ * domain's stream, keep the fastest, and return the shape with its time per
+ * step in ms (the mode is read with lbm_get_solid_writes).  The state is
+ * reset to rest afterwards. */
 lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by, int32_t* zper,
                               double* ms_per_step);
+
+/* Which solid cells a batch step writes; an implementation choice with no
+ * effect on results (fluid cells and wall-link slots hold the same values in
+ * every mode), only on speed.  Where a sphere surface cuts a 128-byte line of
+ * a direction plane, the fluid cells write only part of it; solid cells
+ * sharing the line can complete it (zeros, and copies of their wall-link
+ * slots).  mode 0: fluid cells only (default); 1: also solid cells whose
+ * 64-cell wavefront along x holds a fluid cell; 2: also solid cells whose
+ * line holds a fluid cell.  lbm_batch_autotune picks the fastest.  Invalid
+ * mode: LBM_ERR_INVALID_ARG; mode 1 or 2 on a single domain (whose step
+ * always writes fluid cells only): LBM_ERR_STATE. */
+lbm_status lbm_set_solid_writes(lbm_domain d, int32_t mode);
+lbm_status lbm_get_solid_writes(lbm_domain d, int32_t* mode);
 
 /* Change the pressure drop of a bound domain (state kept). */
 lbm_status lbm_set_delta_rho(lbm_domain d, double delta_rho);

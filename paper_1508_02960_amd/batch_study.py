@@ -52,7 +52,9 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     log(f"[batch] geometry + bind {time.perf_counter() - t0:.1f} s, "
         f"{b.info.n_fluid} fluid cells")
     by, zp, ms = b.autotune(steps=10)
-    log(f"[batch] autotuned shape: rows/block {by}, z planes/block {zp}, {ms:.3f} ms/step")
+    sw = b.solid_writes
+    log(f"[batch] autotuned shape: rows/block {by}, z planes/block {zp}, solid writes {sw}, "
+        f"{ms:.3f} ms/step")
     t1 = time.perf_counter()
     b.run_to_residual(stokes_tol, max_steps)
     r0 = b.results()
@@ -67,6 +69,7 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     b = lbm.Batch(shape, cells, wall="cli", storage="fp32", check_interval=check_interval,
                   device=device)
     b.set_shape(by, zp)
+    b.set_solid_writes(sw)
     t2 = time.perf_counter()
     st, steps, _ = b.run_to_residual(tol, max_steps)
     secs = time.perf_counter() - t2
@@ -77,7 +80,7 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     re = [observables.reynolds_p(u[0], c["diameter"], c["tau"]) for u, c in zip(r["U"], cells)]
     out = dict(n_cells=n_cells, edge=edge, seed=seed, rejected=rejected, tol=tol,
                max_steps=max_steps, shape=dict(rows_per_block=by, z_planes_per_block=zp,
-                                               ms_per_step_all_cells=ms),
+                                               solid_writes=sw, ms_per_step_all_cells=ms),
                stokes_seconds=t_stokes, seconds=secs, status=st,
                mflups=updates / secs / 1e6,
                counts={s: r["status"].count(s) for s in set(r["status"])},

@@ -129,7 +129,15 @@ bool build_geometry(const uint8_t* mask_in, const lbm_sphere* spheres, int ns, i
       for (int x = 0; x < nx; ++x) {
         const int64_t c = x + (int64_t)nx * (y + (int64_t)ny * z);
         if (m[c]) {
-          g.flags[c] = kSolid;
+          // bit k: the fluid node c + e_k pulls direction k from this cell,
+          // so the cell's slot in plane k holds that link's coefficient
+          uint32_t f = kSolid;
+          for (int k = 1; k < kQ; ++k) {
+            const int xn = wrap1(x + kLat.ex[k], nx), yn = wrap1(y + kLat.ey[k], ny),
+                      zn = wrap1(z + kLat.ez[k], nz);
+            if (!m[xn + (int64_t)nx * (yn + (int64_t)ny * zn)]) f |= 1u << k;
+          }
+          g.flags[c] = f;
           continue;
         }
         uint32_t f = 0;

@@ -84,9 +84,10 @@ constexpr MrtBasis make_mrt() {
 
 constexpr MrtBasis kMrt = make_mrt();
 
-// Per-cell flag word: bit k (1..18) set when the pull source c - e_k of
-// direction k is solid (a wall link; the slot of that solid source holds the
-// wall coefficient), kSolid set when the cell itself is solid.
+// Per-cell flag word.  Fluid cell: bit k (1..18) set when the pull source
+// c - e_k of direction k is solid (a wall link; the slot of that solid source
+// in plane k holds the wall coefficient).  Solid cell: kSolid, and bit k set
+// when c + e_k is fluid (this cell's slot in plane k is such a link slot).
 constexpr uint32_t kSolid = 1u << 31;
 constexpr uint32_t kLinkMask = 0x7FFFEu;
 

@@ -57,6 +57,7 @@ struct lbm_domain_s {
   long long cell_size = 0;            // cells per batch cell
   std::vector<lbm_cell_params> cellp;  // per-cell tau, Lambda, delta_rho
   int bby = 0, zper = 1;              // batch launch shape: rows per block, z planes per block
+  int solid_writes = 0;               // which solid cells store (StepParams::solid_writes)
   StepParams* d_cells = nullptr;
   int* d_active = nullptr;      // cells stepped in a residual run
   int* d_active_all = nullptr;  // all ones, for lbm_step
@@ -206,6 +207,7 @@ StepParams step_params(lbm_domain d) {
   sp.s_zeta = d->s_zeta;
   sp.sigma = d->sigma;
   sp.wall = d->p.wall;
+  sp.solid_writes = d->solid_writes;
   sp.seed = hash32((uint32_t)d->step_count ^ hash32((uint32_t)(d->step_count >> 32) + 0x5bd1e995u));
   return sp;
 }
@@ -540,9 +542,11 @@ lbm_status upload_cell_params(lbm_domain d) {
     sp.sigma = 1.0;
     sp.seed = 0;
     sp.wall = d->p.wall;
+    sp.solid_writes = d->solid_writes;
   }
   HIP_OK(d, hipMemcpyAsync(d->d_cells, t.data(), t.size() * sizeof(StepParams),
                            hipMemcpyHostToDevice, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));  // t is a local host buffer
   return LBM_OK;
 }
 
@@ -1323,32 +1327,39 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
   HIP_OK(d, hipEventCreate(&e0));
   HIP_OK(d, hipEventCreate(&e1));
   double best = INFINITY;
-  int best_by = d->bby, best_z = d->zper;
-  for (int by = 1; by * bx <= 1024 && by <= d->geo.ny; by *= 2) {
-    for (int zp = 1; zp <= 8 && zp <= d->geo.nz_cell; zp *= 2) {
-      if (d->geo.nz_cell % zp) continue;
-      d->bby = by;
-      d->zper = zp;
-      st = enqueue_batch_steps(d, 2);
-      if (st != LBM_OK) break;
-      HIP_OK(d, hipEventRecord(e0, d->stream));
-      st = enqueue_batch_steps(d, steps);
-      if (st != LBM_OK) break;
-      HIP_OK(d, hipEventRecord(e1, d->stream));
-      HIP_OK(d, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_OK(d, hipEventElapsedTime(&ms, e0, e1));
-      const double per = ms / steps;
-      if (per < best) {
-        best = per;
-        best_by = by;
-        best_z = zp;
-      }
-    }
+  int best_by = d->bby, best_z = d->zper, best_mode = d->solid_writes;
+  for (int mode = 0; mode <= 2 && st == LBM_OK; ++mode) {
+    d->solid_writes = mode;
+    st = upload_cell_params(d);
     if (st != LBM_OK) break;
+    for (int by = 1; by * bx <= 1024 && by <= d->geo.ny; by *= 2) {
+      for (int zp = 1; zp <= 8 && zp <= d->geo.nz_cell; zp *= 2) {
+        if (d->geo.nz_cell % zp) continue;
+        d->bby = by;
+        d->zper = zp;
+        st = enqueue_batch_steps(d, 2);
+        if (st != LBM_OK) break;
+        HIP_OK(d, hipEventRecord(e0, d->stream));
+        st = enqueue_batch_steps(d, steps);
+        if (st != LBM_OK) break;
+        HIP_OK(d, hipEventRecord(e1, d->stream));
+        HIP_OK(d, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OK(d, hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / steps;
+        if (per < best) {
+          best = per;
+          best_by = by;
+          best_z = zp;
+          best_mode = mode;
+        }
+      }
+      if (st != LBM_OK) break;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  d->solid_writes = best_mode;
   if (st != LBM_OK) return st;
   d->bby = best_by;
   d->zper = best_z;
@@ -1357,6 +1368,21 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
   if (by_out) *by_out = best_by;
   if (zper_out) *zper_out = best_z;
   if (ms_out) *ms_out = best;
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_solid_writes(lbm_domain d, int32_t mode) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  if (mode < 0 || mode > 2) return fail(d, LBM_ERR_INVALID_ARG, "solid_writes must be 0, 1 or 2");
+  if (!d->batch && mode != 0) return fail(d, LBM_ERR_STATE, "solid writes apply to batches");
+  d->solid_writes = mode;
+  if (d->batch && d->ws) return upload_cell_params(d);
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_solid_writes(lbm_domain d, int32_t* mode) {
+  if (!d || !mode) return LBM_ERR_INVALID_ARG;
+  *mode = d->solid_writes;
   return LBM_OK;
 }
 

@@ -28,6 +28,7 @@ EXPORTS = (
     "lbm_drag", "lbm_set_delta_rho", "lbm_synchronize", "lbm_destroy", "lbm_status_string",
     "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
     "lbm_batch_autotune", "lbm_macroscopic_device", "lbm_init_equilibrium_device",
+    "lbm_set_solid_writes", "lbm_get_solid_writes",
 )
 
 
@@ -108,6 +109,8 @@ def library():
         "lbm_batch_results": [vp, vp, vp, vp, vp, vp],
         "lbm_batch_set_shape": [vp, i32, i32],
         "lbm_batch_autotune": [vp, i32, P(i32), P(i32), P(d)],
+        "lbm_set_solid_writes": [vp, i32],
+        "lbm_get_solid_writes": [vp, P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -276,6 +279,16 @@ class Domain:
 
     def synchronize(self) -> None:
         self._check(library().lbm_synchronize(self._h))
+
+    @property
+    def solid_writes(self) -> int:
+        """Which solid cells a batch step writes (0, 1, 2; speed only, see lbm.h)."""
+        m = C.c_int32()
+        self._check(library().lbm_get_solid_writes(self._h, C.byref(m)))
+        return m.value
+
+    def set_solid_writes(self, mode: int) -> None:
+        self._check(library().lbm_set_solid_writes(self._h, int(mode)))
 
     # --------------------------------------------------------- observables
     def macroscopic(self):

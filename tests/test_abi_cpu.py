@@ -113,6 +113,29 @@ def test_unbound_domain_rejects_device_calls():
         lib.lbm_destroy(h)
 
 
+def test_solid_write_mode_is_validated_without_a_gpu():
+    """Solid writes are a batch option: a single domain accepts mode 0 only."""
+    st, h = _create()
+    assert st == 0
+    lib = lbm.library()
+    try:
+        m = C.c_int32(-1)
+        assert lib.lbm_get_solid_writes(h, C.byref(m)) == 0 and m.value == 0
+        assert lib.lbm_set_solid_writes(h, 0) == 0
+        assert lib.lbm_set_solid_writes(h, 2) == 6
+        assert lib.lbm_set_solid_writes(h, 3) == 1
+    finally:
+        lib.lbm_destroy(h)
+    b = lbm.Batch((8, 8, 8), [dict(tau=0.8, delta_rho=1e-4, mask=np.zeros((8, 8, 8), np.uint8))] * 2,
+                  bind=False)
+    for mode in (2, 1, 0):
+        b.set_solid_writes(mode)
+        assert b.solid_writes == mode
+    with pytest.raises(lbm.LbmError):
+        b.set_solid_writes(-1)
+    b.close()
+
+
 def test_info_and_workspace_size():
     shape = (16, 12, 20)
     d = lbm.Domain(shape, tau=0.8, spheres=inputs.centred_sphere(shape, 9.0), bind=False,

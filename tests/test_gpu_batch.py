@@ -85,17 +85,42 @@ def test_batch_run_to_residual_per_cell(orc):
 
 
 def test_batch_shapes_give_identical_bits():
-    """The launch shape chosen by the autotuner changes scheduling only."""
+    """The launch shape and solid-write mode chosen by the autotuner change
+    scheduling only."""
     shape = (16, 10, 14)
     cells = [dict(spheres=inputs.random_spheres(shape, 2, (1.5, 3.0), seed=40 + i),
                   tau=0.6 + 0.2 * i, magic=0.2, delta_rho=1e-3 * (i + 1)) for i in range(3)]
     u0 = inputs.random_velocity((3 * 16, 10, 14), 1e-2, seed=5)
     outs = []
-    for by, zp in [(1, 1), (4, 2), (2, 4)]:
-        b = lbm.Batch(shape, cells, wall="cli", storage="fp32")
+    for by, zp, mode in [(1, 1, 0), (4, 2, 0), (2, 4, 0), (1, 1, 1), (2, 4, 2)]:
+        b = lbm.Batch(shape, cells, wall="cli", storage="fp32", check_interval=10)
         b.set_shape(by, zp)
+        b.set_solid_writes(mode)
         b.init_equilibrium(u0=u0)
         b.step(20)
+        st, _, _ = b.run_to_residual(1e-30, 30)
+        outs.append((b.get_state(), b.results()["U"]))
+        b.close()
+    for g, U in outs[1:]:
+        assert np.array_equal(outs[0][0], g) and np.array_equal(outs[0][1], U)
+
+
+@pytest.mark.parametrize("storage,wall", [("fp64", "cli"), ("fp32", "mr"), ("fp32", "sbb"),
+                                          ("fp64", "libb")])
+def test_batch_solid_write_modes_give_identical_bits(storage, wall):
+    """Rows of 64 cells (one wavefront) cut by spheres: every solid-write
+    mode gives the same state, through CLI and MR also the same wall-link
+    slots."""
+    shape = (8, 12, 64)
+    cells = [dict(spheres=inputs.random_spheres(shape, 3, (3.0, 6.0), seed=70 + i), tau=0.7,
+                  delta_rho=1e-3) for i in range(2)]
+    u0 = inputs.random_velocity((2 * 8, 12, 64), 1e-2, seed=7)
+    outs = []
+    for mode in (0, 1, 2):
+        b = lbm.Batch(shape, cells, wall=wall, storage=storage)
+        b.set_solid_writes(mode)
+        b.init_equilibrium(u0=u0)
+        b.step(15)
         outs.append(b.get_state())
         b.close()
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
@@ -112,7 +137,7 @@ def test_batch_autotune_and_unstable_cell():
                                  for i, c in enumerate(cells)], wall="cli", storage="fp32",
                   check_interval=20)
     by, zp, ms = b.autotune(steps=5)
-    assert by >= 1 and 16 % zp == 0 and ms > 0
+    assert by >= 1 and 16 % zp == 0 and ms > 0 and b.solid_writes in (0, 1, 2)
     assert np.all(b.get_state() == 0)
     st, _, _ = b.run_to_residual(1e-7, 60000)
     r = b.results()
