@@ -42,7 +42,10 @@ def _host(t):
 
 
 SHAPES = [((2, 6, 4, 8), 8, 8), ((1, 4, 6, 4), 16, 24), ((1, 4, 4, 4), 32, 80),
-          ((1, 8, 8, 8), 8, 16)]
+          ((1, 8, 8, 8), 8, 16),
+          # spatially tiled forward path (4 x 8 x 8 tiles, 32-channel chunks):
+          # two batch entries, 64 output channels, and a ragged channel tile
+          ((2, 16, 32, 32), 32, 32), ((1, 16, 32, 64), 64, 64), ((1, 8, 32, 64), 96, 96)]
 
 
 @pytest.mark.parametrize("shape,ci,co", SHAPES)
