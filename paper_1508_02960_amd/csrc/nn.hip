@@ -302,6 +302,139 @@ __global__ __launch_bounds__(256) void conv_fwd_spatial_kernel(const uint16_t* _
   }
 }
 
+// Spatially tiled weight gradient for boxes that are multiples of the
+// 4 x 8 x 8 tile: dw[co][tap][ci] = sum over the voxels v of dy[v][co]
+// x[v + off(tap)][ci], an MFMA GEMM whose K runs over the 256 voxels of a
+// tile.  Block (g, chunk, co tile) adds up the tiles g, g + G, g + 2G, ...
+// (a fixed order) for 16 CT input and 16 RT output channels (channels past
+// ci or co are zero) and writes its sum to part[g]; fold_splits_kernel adds
+// the G partials in order, so the result is deterministic.  Per tile, LDS
+// holds dy transposed (Ds[co][voxel]) and three copies of the 6 x 10 x 10
+// input halo shifted by dx = 0, 1, 2, channel-major (Xs[dx][c][hz][hy][tx]),
+// so that both MFMA operands are 8 consecutive voxels (one x row of the
+// tile) read as one aligned 16-byte word.  Wavefront wv owns the taps wv,
+// wv + 4, ...
+constexpr int kXR = kHZ * kHY * kTX;       // halo positions of one shifted copy of a channel
+constexpr int kDLD = kTZ * kTY * kTX + 8;  // Ds row stride (halfs)
+
+__device__ __forceinline__ void unpack8(uint4 u, uint16_t (&h)[8]) {
+  h[0] = (uint16_t)u.x;
+  h[1] = (uint16_t)(u.x >> 16);
+  h[2] = (uint16_t)u.y;
+  h[3] = (uint16_t)(u.y >> 16);
+  h[4] = (uint16_t)u.z;
+  h[5] = (uint16_t)(u.z >> 16);
+  h[6] = (uint16_t)u.w;
+  h[7] = (uint16_t)(u.w >> 16);
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(256) void conv_bwdw_spatial_kernel(const uint16_t* __restrict__ x,
+                                                                const uint16_t* __restrict__ dy,
+                                                                float* __restrict__ part, Shape s,
+                                                                int ci, int co, int tiles) {
+  constexpr int CC = 16 * CT, OC = 16 * RT;  // input / output channels of the block
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[3 * CC * kXR];
+  __shared__ __attribute__((aligned(16))) uint16_t Ds[OC * kDLD];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, oct = lane >> 4;
+  const int G = gridDim.x, c0 = blockIdx.y * CC, o0 = blockIdx.z * OC;
+  const int tx_n = s.w / kTX, ty_n = s.h / kTY, tz_n = s.d / kTZ;
+  f32x4 acc[7][RT][CT];
+#pragma unroll
+  for (int j = 0; j < 7; ++j)
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[j][r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = blockIdx.x; t < tiles; t += G) {
+    int q = t;
+    const int bx = q % tx_n;
+    q /= tx_n;
+    const int by = q % ty_n;
+    q /= ty_n;
+    const int bz = q % tz_n;
+    const int bn_ = q / tz_n;
+    const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+    __syncthreads();  // the previous tile's reads are done
+    for (int g = tid; g < kHalo * (CC / 8); g += 256) {
+      const int hv = g / (CC / 8), p8 = 8 * (g % (CC / 8));
+      const int hz = hv / (kHY * kHX), hy = (hv / kHX) % kHY, hx = hv % kHX;
+      int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+      zz = zz < 0 ? zz + s.d : (zz >= s.d ? zz - s.d : zz);
+      yy = yy < 0 ? yy + s.h : (yy >= s.h ? yy - s.h : yy);
+      xx = xx < 0 ? xx + s.w : (xx >= s.w ? xx - s.w : xx);
+      const long long v = (((long long)bn_ * s.d + zz) * s.h + yy) * s.w + xx;
+      uint16_t h[8];
+      unpack8(c0 + p8 < ci ? *reinterpret_cast<const uint4*>(x + v * ci + c0 + p8)
+                           : make_uint4(0, 0, 0, 0),
+              h);
+      const int pos = (hz * kHY + hy) * kTX;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int tx = hx - dx;
+        if (tx < 0 || tx >= kTX) continue;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Xs[(dx * CC + p8 + i) * kXR + pos + tx] = h[i];
+      }
+    }
+    for (int g = tid; g < kTZ * kTY * kTX * (OC / 8); g += 256) {
+      const int r = g / (OC / 8), p8 = 8 * (g % (OC / 8));
+      const int tz = r >> 6, ty = (r >> 3) & 7, tx = r & 7;
+      const long long v = (((long long)bn_ * s.d + z0 + tz) * s.h + y0 + ty) * s.w + x0 + tx;
+      uint16_t h[8];
+      unpack8(o0 + p8 < co ? *reinterpret_cast<const uint4*>(dy + v * co + o0 + p8)
+                           : make_uint4(0, 0, 0, 0),
+              h);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Ds[(p8 + i) * kDLD + r] = h[i];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < 8; ++ks) {
+      const int vr = 4 * ks + oct;  // x row (tz, ty) of this lane's 8 voxels
+      const int tz = vr >> 3, ty = vr & 7;
+      bf16x8 a[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        a[rt] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&Ds[(16 * rt + (lane & 15)) * kDLD + 8 * vr]));
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const int tap = wv + 4 * j;
+        if (tap >= 27) continue;
+        const int dz = tap / 9, dyy = (tap / 3) % 3, dx = tap % 3;
+        const int pos = ((tz + dz) * kHY + ty + dyy) * kTX;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const bf16x8 b = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(
+                          &Xs[(dx * CC + 16 * ct + (lane & 15)) * kXR + pos]));
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+            acc[j][rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[j][rt][ct], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // result rows (co) 4 (lane / 16) + i of row tile rt, column (ci) lane & 15
+  const long long base = (long long)blockIdx.x * co * 27 * ci;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const int tap = wv + 4 * j;
+    if (tap >= 27) continue;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + 16 * rt + 4 * oct + i, c = c0 + 16 * ct + (lane & 15);
+          if (o < co && c < ci) part[base + ((long long)o * 27 + tap) * ci + c] = acc[j][rt][ct][i];
+        }
+  }
+}
+
 // wt[ci][tap][co] = w[co][26 - tap][ci]: the backward-data convolution is the
 // forward convolution of dy with these weights (mirrored taps, swapped roles).
 __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt,
@@ -475,6 +608,7 @@ __global__ void fold_splits_kernel(const float* __restrict__ part, float* __rest
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     float a = 0.f;
+#pragma unroll 8
     for (int s = 0; s < splits; ++s) a += part[(long long)s * n + i];
     dw[i] = a;
   }
@@ -759,10 +893,28 @@ NN_API lbm_status nn_conv3d_backward_data(const void* dy, const void* wt, float*
   return nn_conv3d_forward(dy, wt, nullptr, dx, n, d, h, wd, co, ci, stream);
 }
 
+// The spatially tiled weight gradient applies (and with how many splits).
+static bool bwdw_spatial(int n, int d, int h, int wd, int ci, int co, int* splits) {
+  const long long tiles = (long long)n * d * h * wd / (kTZ * kTY * kTX);
+  if (d % kTZ || h % kTY || wd % kTX || tiles < 256) return false;
+  // about 512 blocks over the channel tiles, at least two voxel tiles each
+  const int ct = ci % 32 == 0 ? 32 : 16, rt = co % 32 == 0 ? 32 : 16;
+  const long long chan_tiles = (long long)((ci + ct - 1) / ct) * ((co + rt - 1) / rt);
+  *splits = (int)std::max<long long>(
+      1, std::min<long long>({256, tiles / 2, 512 / std::max<long long>(chan_tiles, 1)}));
+  return true;
+}
+
 NN_API lbm_status nn_conv3d_backward_weight_workspace(int n, int d, int h, int wd, int ci, int co,
                                                       size_t* bytes, int* splits) {
   if (!bytes || bad_shape(n, d, h, wd) || ci < 8 || ci % 8 || co < 8 || co % 8)
     return LBM_ERR_INVALID_ARG;
+  int ssp = 0;
+  if (bwdw_spatial(n, d, h, wd, ci, co, &ssp)) {
+    *bytes = (size_t)ssp * co * 27 * ci * sizeof(float);
+    if (splits) *splits = ssp;
+    return LBM_OK;
+  }
   const long long m = (long long)n * d * h * wd;
   const int tm = co <= 32 ? 32 : 64;
   const long long tiles = (long long)((co + tm - 1) / tm) * ((27 * ci + 63) / 64);
@@ -783,6 +935,30 @@ NN_API lbm_status nn_conv3d_backward_weight(const void* x, const void* dy, float
   if (st != LBM_OK) return st;
   if (!x || !dy || !dw || !ws || ws_bytes < need) return LBM_ERR_WORKSPACE;
   const Shape s = shape_of(n, d, h, wd);
+  const long long nw = (long long)co * 27 * ci;
+  int ssp = 0;
+  if (bwdw_spatial(n, d, h, wd, ci, co, &ssp)) {
+    const int tiles = (int)(s.m / (kTZ * kTY * kTX));
+    // channel tiles: 32 where the count is a multiple of 32, else 16 (zero padded)
+    const int ct = ci % 32 == 0 ? 2 : 1, rt = co % 32 == 0 ? 2 : 1;
+    dim3 sgrid((unsigned)ssp, (unsigned)((ci + 16 * ct - 1) / (16 * ct)),
+               (unsigned)((co + 16 * rt - 1) / (16 * rt)));
+    const uint16_t* xx = (const uint16_t*)x;
+    const uint16_t* dd = (const uint16_t*)dy;
+    float* pp = (float*)ws;
+    const hipStream_t st = (hipStream_t)stream;
+    if (rt == 2 && ct == 2)
+      conv_bwdw_spatial_kernel<2, 2><<<sgrid, 256, 0, st>>>(xx, dd, pp, s, ci, co, tiles);
+    else if (rt == 2)
+      conv_bwdw_spatial_kernel<2, 1><<<sgrid, 256, 0, st>>>(xx, dd, pp, s, ci, co, tiles);
+    else if (ct == 2)
+      conv_bwdw_spatial_kernel<1, 2><<<sgrid, 256, 0, st>>>(xx, dd, pp, s, ci, co, tiles);
+    else
+      conv_bwdw_spatial_kernel<1, 1><<<sgrid, 256, 0, st>>>(xx, dd, pp, s, ci, co, tiles);
+    fold_splits_kernel<<<grid_for(nw), 256, 0, (hipStream_t)stream>>>((const float*)ws, dw, nw,
+                                                                       ssp);
+    return check_launch();
+  }
   const long long chunks = (s.m + kWM - 1) / kWM;
   const long long per = (chunks + sp - 1) / sp;
   const int tm = co <= 32 ? 32 : 64;
@@ -793,7 +969,6 @@ NN_API lbm_status nn_conv3d_backward_weight(const void* x, const void* dy, float
   else
     conv_bwdw_kernel<64><<<grid, 256, 0, (hipStream_t)stream>>>(
         (const uint16_t*)x, (const uint16_t*)dy, (float*)ws, s, ci, co, per);
-  const long long nw = (long long)co * 27 * ci;
   fold_splits_kernel<<<grid_for(nw), 256, 0, (hipStream_t)stream>>>((const float*)ws, dw, nw, sp);
   return check_launch();
 }
