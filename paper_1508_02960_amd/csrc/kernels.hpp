@@ -111,21 +111,15 @@ struct Storage<fp16s_t> {
   static constexpr bool stochastic = true;
   __device__ __host__ static float to_float(fp16s_t v) { return (float)v.v; }
   __device__ __host__ static fp16s_t from_float(float v) { return fp16s_t{(_Float16)v}; }
-  // Integer form: below the FP16 spacing of |f| lie `drop` bits of the FP32
-  // pattern (13 in the normal range, more below 2^-14); adding a uniform
-  // random number of that width to the magnitude and clearing those bits
-  // gives the lower or upper neighbour with the right probabilities (a carry
-  // into the exponent is the next power of two).  Magnitudes below 2^-24,
-  // far under the scaled range, round to nearest.
+  // gfx950's stochastic-rounding conversion (v_cvt_sr_f16_f32): the top bits
+  // of r, as many as the FP32 pattern carries below the FP16 spacing of |f|,
+  // are added to those bits before truncation, so the value rounds up with
+  // probability equal to its distance from the lower neighbour (checked on
+  // the device: always a neighbour, unbiased, decided by the high bits).
   __device__ static fp16s_t from_float_sr(float f, uint32_t r) {
-    const uint32_t b = __builtin_bit_cast(uint32_t, f);
-    const uint32_t mag = b & 0x7FFFFFFFu;
-    const int e = (int)(mag >> 23) - 127;
-    if (mag >= 0x477FE000u || e < -24) return fp16s_t{(_Float16)f};  // >= 65504, inf, NaN, tiny
-    const int drop = e < -14 ? -1 - e : 13;
-    const uint32_t mask = (1u << drop) - 1u;
-    const uint32_t q = (mag + (r >> (32 - drop))) & ~mask;
-    return fp16s_t{(_Float16)__builtin_bit_cast(float, q | (b & 0x80000000u))};
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = __builtin_amdgcn_cvt_sr_f16_f32(h2{0, 0}, f, r, false);
+    return fp16s_t{v[0]};
   }
 };
 template <>
@@ -139,13 +133,13 @@ struct Storage<bf16s_t> {
   __device__ __host__ static bf16s_t from_float(float f) {
     return bf16s_t{Storage<bf16_t>::from_float(f).u};
   }
-  // BF16 is the top half of FP32 (sign-magnitude): adding a random 16-bit
-  // word to the magnitude bits and truncating rounds the magnitude
-  // stochastically.
+  // BF16 is the top half of FP32: gfx950's v_cvt_sr_bf16_f32 adds the top
+  // 16 bits of r to the low half of the pattern and truncates, which rounds
+  // the magnitude stochastically.
   __device__ static bf16s_t from_float_sr(float f, uint32_t r) {
-    const uint32_t b = __builtin_bit_cast(uint32_t, f);
-    if ((b & 0x7F800000u) == 0x7F800000u) return from_float(f);
-    return bf16s_t{(uint16_t)((b + (r >> 16)) >> 16)};
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const b2 v = __builtin_amdgcn_cvt_sr_bf16_f32(b2{0, 0}, f, r, false);
+    return bf16s_t{__builtin_bit_cast(uint16_t, v[0])};
   }
 };
 
