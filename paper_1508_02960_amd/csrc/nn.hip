@@ -845,6 +845,121 @@ Shape shape_of(int n, int d, int h, int w) {
 
 bool bad_shape(int n, int d, int h, int w) { return n < 1 || d < 1 || h < 1 || w < 1; }
 
+// Granule forms of the pooling, upsampling, concatenation and split kernels:
+// one thread moves 8 BF16 (or 4 FP32) channels of a voxel as one 16-byte
+// word, with 32-bit index arithmetic.  Used when the channel counts are
+// multiples of the granule, the pointers 16-byte aligned and the element
+// count below 2^31; the element forms above cover the rest.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+__device__ __forceinline__ void voxel_of(int v, int d, int h, int w, int& n, int& z, int& y,
+                                         int& x) {
+  x = v % w;
+  v /= w;
+  y = v % h;
+  v /= h;
+  z = v % d;
+  n = v / d;
+}
+
+__global__ void pool_fwd_vec_kernel(const uint4* __restrict__ x, uint4* __restrict__ y, int n_,
+                                    int d, int h, int w, int g) {
+  const int qd = d / 2, qh = h / 2, qw = w / 2;
+  const int total = n_ * qd * qh * qw * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int gi = i % g;
+    int vn, vz, vy, vx;
+    voxel_of(i / g, qd, qh, qw, vn, vz, vy, vx);
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int o = 0; o < 8; ++o) {
+      const int f = ((vn * d + 2 * vz + (o >> 2)) * h + 2 * vy + ((o >> 1) & 1)) * w + 2 * vx + (o & 1);
+      const uint4 u = x[f * g + gi];
+      const uint32_t q[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a[2 * k] += bf2f((uint16_t)q[k]);
+        a[2 * k + 1] += bf2f((uint16_t)(q[k] >> 16));
+      }
+    }
+    uint32_t r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      r[k] = (uint32_t)f2bf(0.125f * a[2 * k]) | ((uint32_t)f2bf(0.125f * a[2 * k + 1]) << 16);
+    y[i] = make_uint4(r[0], r[1], r[2], r[3]);
+  }
+}
+
+__global__ void pool_bwd_vec_kernel(const float4* __restrict__ dy, float4* __restrict__ dx,
+                                    int n_, int d, int h, int w, int g) {
+  const int total = n_ * d * h * w * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int gi = i % g;
+    int vn, vz, vy, vx;
+    voxel_of(i / g, d, h, w, vn, vz, vy, vx);
+    const int p = ((vn * (d / 2) + vz / 2) * (h / 2) + vy / 2) * (w / 2) + vx / 2;
+    const float4 v = dy[p * g + gi];
+    dx[i] = make_float4(0.125f * v.x, 0.125f * v.y, 0.125f * v.z, 0.125f * v.w);
+  }
+}
+
+// coarse (n, d, h, w) -> fine (n, 2d, 2h, 2w)
+__global__ void up_fwd_vec_kernel(const uint4* __restrict__ x, uint4* __restrict__ y, int n_,
+                                  int d, int h, int w, int g) {
+  const int total = n_ * 8 * d * h * w * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int gi = i % g;
+    int vn, vz, vy, vx;
+    voxel_of(i / g, 2 * d, 2 * h, 2 * w, vn, vz, vy, vx);
+    const int p = ((vn * d + vz / 2) * h + vy / 2) * w + vx / 2;
+    y[i] = x[p * g + gi];
+  }
+}
+
+__global__ void up_bwd_vec_kernel(const float4* __restrict__ dy, float4* __restrict__ dx, int n_,
+                                  int d, int h, int w, int g) {
+  const int total = n_ * d * h * w * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int gi = i % g;
+    int vn, vz, vy, vx;
+    voxel_of(i / g, d, h, w, vn, vz, vy, vx);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int o = 0; o < 8; ++o) {
+      const int f = ((vn * 2 * d + 2 * vz + (o >> 2)) * 2 * h + 2 * vy + ((o >> 1) & 1)) * 2 * w +
+                    2 * vx + (o & 1);
+      const float4 v = dy[f * g + gi];
+      a.x += v.x;
+      a.y += v.y;
+      a.z += v.z;
+      a.w += v.w;
+    }
+    dx[i] = a;
+  }
+}
+
+// granules of 8 bf16 channels: ga + gb per voxel
+__global__ void concat_vec_kernel(const uint4* __restrict__ a, const uint4* __restrict__ b,
+                                  uint4* __restrict__ y, int m, int ga, int gb) {
+  const int g = ga + gb, total = m * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int v = i / g, k = i % g;
+    y[i] = k < ga ? a[v * ga + k] : b[v * gb + k - ga];
+  }
+}
+
+// granules of 4 fp32 channels
+__global__ void split_vec_kernel(const float4* __restrict__ dy, float4* __restrict__ da,
+                                 float4* __restrict__ db, int m, int ga, int gb) {
+  const int g = ga + gb, total = m * g;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int v = i / g, k = i % g;
+    if (k < ga) {
+      if (da) da[v * ga + k] = dy[i];
+    } else if (db) {
+      db[v * gb + k - ga] = dy[i];
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -1020,6 +1135,11 @@ NN_API lbm_status nn_pool2_forward(const void* x, void* y, int n, int d, int h, 
   if (!x || !y || bad_shape(n, d, h, w) || d % 2 || h % 2 || w % 2 || c < 1)
     return LBM_ERR_INVALID_ARG;
   const Shape s = shape_of(n, d, h, w);
+  if (c % 8 == 0 && aligned16(x) && aligned16(y) && s.m * c < (1LL << 31)) {
+    pool_fwd_vec_kernel<<<grid_for(s.m / 8 * (c / 8)), 256, 0, (hipStream_t)stream>>>(
+        (const uint4*)x, (uint4*)y, n, d, h, w, c / 8);
+    return check_launch();
+  }
   pool_fwd_kernel<<<grid_for(s.m / 8 * c), 256, 0, (hipStream_t)stream>>>(
       (const uint16_t*)x, (uint16_t*)y, s, c);
   return check_launch();
@@ -1030,6 +1150,11 @@ NN_API lbm_status nn_pool2_backward(const float* dy, float* dx, int n, int d, in
   if (!dy || !dx || bad_shape(n, d, h, w) || d % 2 || h % 2 || w % 2 || c < 1)
     return LBM_ERR_INVALID_ARG;
   const Shape s = shape_of(n, d, h, w);
+  if (c % 4 == 0 && aligned16(dy) && aligned16(dx) && s.m * c < (1LL << 31)) {
+    pool_bwd_vec_kernel<<<grid_for(s.m * (c / 4)), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)dy, (float4*)dx, n, d, h, w, c / 4);
+    return check_launch();
+  }
   pool_bwd_kernel<<<grid_for(s.m * c), 256, 0, (hipStream_t)stream>>>(dy, dx, s, c);
   return check_launch();
 }
@@ -1038,6 +1163,11 @@ NN_API lbm_status nn_upsample2_forward(const void* x, void* y, int n, int d, int
                                        void* stream) {
   if (!x || !y || bad_shape(n, d, h, w) || c < 1) return LBM_ERR_INVALID_ARG;
   const Shape q = shape_of(n, d, h, w);
+  if (c % 8 == 0 && aligned16(x) && aligned16(y) && q.m * 8 * c < (1LL << 31)) {
+    up_fwd_vec_kernel<<<grid_for(q.m * 8 * (c / 8)), 256, 0, (hipStream_t)stream>>>(
+        (const uint4*)x, (uint4*)y, n, d, h, w, c / 8);
+    return check_launch();
+  }
   up_fwd_kernel<<<grid_for(q.m * 8 * c), 256, 0, (hipStream_t)stream>>>(
       (const uint16_t*)x, (uint16_t*)y, q, c);
   return check_launch();
@@ -1047,6 +1177,11 @@ NN_API lbm_status nn_upsample2_backward(const float* dy, float* dx, int n, int d
                                         int c, void* stream) {
   if (!dy || !dx || bad_shape(n, d, h, w) || c < 1) return LBM_ERR_INVALID_ARG;
   const Shape q = shape_of(n, d, h, w);
+  if (c % 4 == 0 && aligned16(dy) && aligned16(dx) && q.m * 8 * c < (1LL << 31)) {
+    up_bwd_vec_kernel<<<grid_for(q.m * (c / 4)), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)dy, (float4*)dx, n, d, h, w, c / 4);
+    return check_launch();
+  }
   up_bwd_kernel<<<grid_for(q.m * c), 256, 0, (hipStream_t)stream>>>(dy, dx, q, c);
   return check_launch();
 }
@@ -1054,6 +1189,12 @@ NN_API lbm_status nn_upsample2_backward(const float* dy, float* dx, int n, int d
 NN_API lbm_status nn_concat_channels(const void* a, const void* b, void* y, long long m, int ca,
                                      int cb, void* stream) {
   if (!a || !b || !y || m < 1 || ca < 1 || cb < 1) return LBM_ERR_INVALID_ARG;
+  if (ca % 8 == 0 && cb % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(y) &&
+      m * (ca + cb) < (1LL << 31)) {
+    concat_vec_kernel<<<grid_for(m * ((ca + cb) / 8)), 256, 0, (hipStream_t)stream>>>(
+        (const uint4*)a, (const uint4*)b, (uint4*)y, (int)m, ca / 8, cb / 8);
+    return check_launch();
+  }
   concat_kernel<<<grid_for(m * (ca + cb)), 256, 0, (hipStream_t)stream>>>(
       (const uint16_t*)a, (const uint16_t*)b, (uint16_t*)y, m, ca, cb);
   return check_launch();
@@ -1062,6 +1203,12 @@ NN_API lbm_status nn_concat_channels(const void* a, const void* b, void* y, long
 NN_API lbm_status nn_split_channels(const float* dy, float* da, float* db, long long m, int ca,
                                     int cb, void* stream) {
   if (!dy || m < 1 || ca < 1 || cb < 1) return LBM_ERR_INVALID_ARG;
+  if (ca % 4 == 0 && cb % 4 == 0 && aligned16(dy) && aligned16(da) && aligned16(db) &&
+      m * (ca + cb) < (1LL << 31)) {
+    split_vec_kernel<<<grid_for(m * ((ca + cb) / 4)), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)dy, (float4*)da, (float4*)db, (int)m, ca / 4, cb / 4);
+    return check_launch();
+  }
   split_kernel<<<grid_for(m * (ca + cb)), 256, 0, (hipStream_t)stream>>>(dy, da, db, m, ca, cb);
   return check_launch();
 }

@@ -95,36 +95,38 @@ def test_conv_forward_backward_match_reference(ctx, shape, ci, co):
         assert rel(_host(db), db_ref) < 1e-5
 
 
-def test_pool_up_concat_split_relu(ctx):
+@pytest.mark.parametrize("c", [8, 6])
+def test_pool_up_concat_split_relu(ctx, c):
+    """c = 8: the 16-byte granule kernels; c = 6: the element kernels."""
     rng = np.random.default_rng(3)
     lib = W._nn()
     s = ctx.stream
-    x = R.bf16(rng.standard_normal((2, 4, 6, 8, 8)))
-    y = ctx.bf(2, 2, 3, 4, 8)
-    assert lib.nn_pool2_forward(W._p(_bf_dev(ctx, x)), W._p(y), 2, 4, 6, 8, 8, s) == 0
+    x = R.bf16(rng.standard_normal((2, 4, 6, 8, c)))
+    y = ctx.bf(2, 2, 3, 4, c)
+    assert lib.nn_pool2_forward(W._p(_bf_dev(ctx, x)), W._p(y), 2, 4, 6, 8, c, s) == 0
     assert rel(_host(y), R.bf16(R.pool2(x))) < 1e-6
-    dy = rng.standard_normal((2, 2, 3, 4, 8))
-    dx = ctx.f32(2, 4, 6, 8, 8)
-    assert lib.nn_pool2_backward(W._p(_f_dev(ctx, dy)), W._p(dx), 2, 4, 6, 8, 8, s) == 0
+    dy = rng.standard_normal((2, 2, 3, 4, c))
+    dx = ctx.f32(2, 4, 6, 8, c)
+    assert lib.nn_pool2_backward(W._p(_f_dev(ctx, dy)), W._p(dx), 2, 4, 6, 8, c, s) == 0
     assert rel(_host(dx), R.pool2_backward(dy)) < 1e-6
-    xc = R.bf16(rng.standard_normal((1, 2, 3, 2, 8)))
-    yf = ctx.bf(1, 4, 6, 4, 8)
-    assert lib.nn_upsample2_forward(W._p(_bf_dev(ctx, xc)), W._p(yf), 1, 2, 3, 2, 8, s) == 0
+    xc = R.bf16(rng.standard_normal((1, 2, 3, 2, c)))
+    yf = ctx.bf(1, 4, 6, 4, c)
+    assert lib.nn_upsample2_forward(W._p(_bf_dev(ctx, xc)), W._p(yf), 1, 2, 3, 2, c, s) == 0
     assert np.array_equal(_host(yf), R.up2(xc))
-    dyf = rng.standard_normal((1, 4, 6, 4, 8))
-    dxc = ctx.f32(1, 2, 3, 2, 8)
-    assert lib.nn_upsample2_backward(W._p(_f_dev(ctx, dyf)), W._p(dxc), 1, 2, 3, 2, 8, s) == 0
+    dyf = rng.standard_normal((1, 4, 6, 4, c))
+    dxc = ctx.f32(1, 2, 3, 2, c)
+    assert lib.nn_upsample2_backward(W._p(_f_dev(ctx, dyf)), W._p(dxc), 1, 2, 3, 2, c, s) == 0
     assert rel(_host(dxc), R.up2_backward(dyf)) < 1e-6
-    a = R.bf16(rng.standard_normal((5, 8)))
-    b = R.bf16(rng.standard_normal((5, 16)))
-    cat = ctx.bf(5, 24)
-    assert lib.nn_concat_channels(W._p(_bf_dev(ctx, a)), W._p(_bf_dev(ctx, b)), W._p(cat), 5, 8,
-                                  16, s) == 0
+    a = R.bf16(rng.standard_normal((5, c)))
+    b = R.bf16(rng.standard_normal((5, 2 * c)))
+    cat = ctx.bf(5, 3 * c)
+    assert lib.nn_concat_channels(W._p(_bf_dev(ctx, a)), W._p(_bf_dev(ctx, b)), W._p(cat), 5, c,
+                                  2 * c, s) == 0
     assert np.array_equal(_host(cat), np.concatenate([a, b], axis=1))
-    g = rng.standard_normal((5, 24))
-    ga, gb = ctx.f32(5, 8), ctx.f32(5, 16)
-    assert lib.nn_split_channels(W._p(_f_dev(ctx, g)), W._p(ga), W._p(gb), 5, 8, 16, s) == 0
-    assert rel(_host(ga), g[:, :8]) < 1e-7 and rel(_host(gb), g[:, 8:]) < 1e-7
+    g = rng.standard_normal((5, 3 * c))
+    ga, gb = ctx.f32(5, c), ctx.f32(5, 2 * c)
+    assert lib.nn_split_channels(W._p(_f_dev(ctx, g)), W._p(ga), W._p(gb), 5, c, 2 * c, s) == 0
+    assert rel(_host(ga), g[:, :c]) < 1e-7 and rel(_host(gb), g[:, c:]) < 1e-7
     z = rng.standard_normal(1000)
     act = ctx.bf(1000)
     assert lib.nn_activation_forward(W._p(_f_dev(ctx, z)), W._p(act), 1000, 1, s) == 0
