@@ -255,6 +255,32 @@ __device__ __forceinline__ void collide_trt(C* g, C wp, C wm) {
 // MRT (eq. (MRT)) as g* = g - M^-1 S M (g - g^eq) with M^-1 = M^T diag(1/|M_i|^2).
 // M is a compile-time constant; the unrolled products fold its zeros.
 // Conserved moments (rows 0, 3, 5, 7) carry no non-equilibrium part.
+// Rows of M that are even under e -> -e (the rest are odd).  The moving
+// directions form 9 opposite pairs (kPairA[p], opp), so an even row sees only
+// the pair sums and an odd row only the pair differences, and the
+// back-transform of a pair is one even and one odd sum: about half the
+// multiply-adds of the dense product.
+constexpr bool mrt_even_row(int i) { return i <= 2 || (i >= 9 && i <= 15); }
+constexpr int kPairA[9] = {1, 3, 5, 7, 8, 11, 12, 15, 16};
+
+constexpr bool mrt_pair_structure_holds() {
+  bool seen[kQ] = {};
+  for (int p = 0; p < 9; ++p) {
+    const int a = kPairA[p], b = kLat.opp[a];
+    if (a == b || seen[a] || seen[b]) return false;
+    seen[a] = seen[b] = true;
+  }
+  for (int i = 0; i < kQ; ++i) {
+    if (!mrt_even_row(i) && kMrt.m[i][0] != 0.0) return false;
+    for (int k = 1; k < kQ; ++k) {
+      const double sgn = mrt_even_row(i) ? 1.0 : -1.0;
+      if (kMrt.m[i][k] != sgn * kMrt.m[i][kLat.opp[k]]) return false;
+    }
+  }
+  return true;
+}
+static_assert(mrt_pair_structure_holds(), "MRT rows must be even or odd over opposite pairs");
+
 template <typename C>
 __device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
   C rho, ux, uy, uz;
@@ -266,6 +292,14 @@ __device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
   LBM_D(1) LBM_D(2) LBM_D(3) LBM_D(4) LBM_D(5) LBM_D(6) LBM_D(7) LBM_D(8) LBM_D(9)
   LBM_D(10) LBM_D(11) LBM_D(12) LBM_D(13) LBM_D(14) LBM_D(15) LBM_D(16) LBM_D(17) LBM_D(18)
 #undef LBM_D
+  // pair sums and differences of the non-equilibrium part
+  C ps[9], pd[9];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    ps[p] = d[kPairA[p]] + d[kLat.opp[kPairA[p]]];
+    pd[p] = d[kPairA[p]] - d[kLat.opp[kPairA[p]]];
+  }
+  // relaxed moments r_i = s_i (M d)_i / |M_i|^2 (conserved moments: 0)
   C r[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -274,24 +308,43 @@ __device__ __forceinline__ void collide_mrt(C* g, C s_nu, C s_e, C s_zeta) {
       continue;
     }
     C m = (C)0;
+    if (mrt_even_row(i)) {
+      if (kMrt.m[i][0] != 0.0) m += (C)kMrt.m[i][0] * d[0];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-      if (kMrt.m[i][k] != 0.0) m += (C)kMrt.m[i][k] * d[k];
+      for (int p = 0; p < 9; ++p)
+        if (kMrt.m[i][kPairA[p]] != 0.0) m += (C)kMrt.m[i][kPairA[p]] * ps[p];
+    } else {
+#pragma unroll
+      for (int p = 0; p < 9; ++p)
+        if (kMrt.m[i][kPairA[p]] != 0.0) m += (C)kMrt.m[i][kPairA[p]] * pd[p];
     }
     const C s = (i == 1 || i == 2) ? s_e
                 : (i == 9 || i == 11 || i == 13 || i == 14 || i == 15) ? s_nu
                                                                      : s_zeta;
     r[i] = s * m * (C)(1.0 / kMrt.n2[i]);
   }
-#pragma unroll
-  for (int k = 0; k < kQ; ++k) {
+  // g_k -= sum_i M_ik r_i, as an even and an odd part per pair
+  {
     C a = (C)0;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      if (i == 0 || i == 3 || i == 5 || i == 7) continue;
-      if (kMrt.m[i][k] != 0.0) a += (C)kMrt.m[i][k] * r[i];
+    for (int i = 1; i < kQ; ++i)
+      if (mrt_even_row(i) && kMrt.m[i][0] != 0.0) a += (C)kMrt.m[i][0] * r[i];
+    g[0] = g[0] - a;
+  }
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const int ka = kPairA[p], kb = kLat.opp[ka];
+    C ae = (C)0, ao = (C)0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      if (i == 3 || i == 5 || i == 7 || kMrt.m[i][ka] == 0.0) continue;
+      if (mrt_even_row(i))
+        ae += (C)kMrt.m[i][ka] * r[i];
+      else
+        ao += (C)kMrt.m[i][ka] * r[i];
     }
-    g[k] = g[k] - a;
+    g[ka] = g[ka] - (ae + ao);
+    g[kb] = g[kb] - (ae - ao);
   }
 }
 
