@@ -475,18 +475,23 @@ __device__ __forceinline__ void stored_moments(const S* __restrict__ src, long l
 // rule that needs a solid node falls back: x_f2 solid -> bounce-back (LIBB
 // and QIBB with q >= 1/2 keep LIBB's q >= 1/2 branch, which needs x_f1
 // only); x_f3 solid -> LIBB (from QIBB) or CLI (from MR).  Unscaled storage
-// (FP32, FP64) only.
+// (FP32, FP64) only.  m1 holds the density deviation and velocity of the
+// stored state at x (IEBB only; the caller computes them once per node).
 template <typename S, typename C>
 __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __restrict__ flags,
-                                const StepParams& p, int x, int y, int z, int c, int k, C q) {
+                                const StepParams& p, int x, int y, int z, int c, int k, C q,
+                                uint32_t fl, const C (&m1)[4]) {
   const long long st = p.stride;
   const int j = kLat.opp[k];
   const C own_j = (C)Storage<S>::to_float(src[j * st + c]);
   const C own_k = (C)Storage<S>::to_float(src[k * st + c]);
   const FarNode n2 = far_node(p, x, y, z, k, 1);
   const FarNode n3 = far_node(p, x, y, z, k, 2);
-  const bool f2 = !(flags[n2.c] & kSolid);
-  const bool f3 = f2 && !(flags[n3.c] & kSolid);
+  // x_f2 = x - e_j is the pull source of direction j here, and x_f3 that of
+  // direction j at x_f2, so the flag bits j of x and of x_f2 tell if they
+  // are solid
+  const bool f2 = !(fl & (1u << j));
+  const bool f3 = f2 && !(flags[n2.c] & (1u << j));
   int rule = p.wall;
   if (rule == kRuleMR && !f3) rule = kRuleCLI;
   if (rule == kRuleQIBB && (q < (C)0.5 ? !f3 : !f2)) rule = kRuleLIBB;
@@ -511,8 +516,8 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       return (two * q - one) / q * own_k + own_j / (q * (two * q + one)) +
              (one - two * q) / (two * q + one) * far_value<S, C>(src, st, p, n2, k);
     case kRuleIEBB: {
-      C drho1, u1[3], ubf[3], X;
-      stored_moments<S, C>(src, st, c, drho1, u1);
+      const C drho1 = m1[0], u1[3] = {m1[1], m1[2], m1[3]};
+      C ubf[3], X;
       const C tau = (C)(1.0 / p.omega_p);
       if (q < (C)0.5) {
         if (!f2) return own_j;
@@ -585,14 +590,25 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
   for (int k = 0; k < kQ; ++k)
     g[k] = (C)St::to_float(src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])]);
 
-  // wall links: the pulled raw value is the stored coefficient a
+  // wall links: the pulled raw value is the stored coefficient a (CLI) or
+  // the wall distance q (general rules)
   if (fl & kLinkMask) {
+    C m1[4] = {(C)0, (C)0, (C)0, (C)0};
+    if constexpr (WALL == kGEN) {
+      if (p.wall == kRuleIEBB) {
+        C u1[3];
+        stored_moments<S, C>(src, st, c, m1[0], u1);
+        m1[1] = u1[0];
+        m1[2] = u1[1];
+        m1[3] = u1[2];
+      }
+    }
 #pragma unroll
     for (int k = 1; k < kQ; ++k) {
       if (fl & (1u << k)) {
         if constexpr (WALL == kGEN) {
           // the pulled raw value is the link's wall distance q
-          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k]);
+          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1);
           continue;
         }
         const int j = kLat.opp[k];
@@ -1011,6 +1027,16 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
     const uint32_t fl = flags[c];
     if ((fl & kSolid) || !(fl & kLinkMask)) continue;
     const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / (p.nx * p.ny);
+    double m1[4] = {0, 0, 0, 0};
+    if constexpr (WALL == kGEN) {
+      if (p.wall == kRuleIEBB) {
+        double u1[3];
+        stored_moments<S, double>(src, st, c, m1[0], u1);
+        m1[1] = u1[0];
+        m1[2] = u1[1];
+        m1[3] = u1[2];
+      }
+    }
     for (int k = 1; k < kQ; ++k) {
       if (!(fl & (1u << k))) continue;
       const int j = kLat.opp[k];
@@ -1020,7 +1046,7 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
         const double q = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
-        back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q);
+        back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1);
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
