@@ -480,7 +480,7 @@ __device__ __forceinline__ void stored_moments(const S* __restrict__ src, long l
 template <typename S, typename C>
 __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __restrict__ flags,
                                 const StepParams& p, int x, int y, int z, int c, int k, C q,
-                                uint32_t fl, const C (&m1)[4]) {
+                                uint32_t fl, const C (&m1)[4], C pulled_j) {
   const long long st = p.stride;
   const int j = kLat.opp[k];
   const C own_j = (C)Storage<S>::to_float(src[j * st + c]);
@@ -492,6 +492,14 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
   // are solid
   const bool f2 = !(fl & (1u << j));
   const bool f3 = f2 && !(flags[n2.c] & (1u << j));
+  // g_j at x_f2 is this node's pull in direction j (pulled_j, raw); with the
+  // jump of a read across the x-periodic plane
+  C f2_j = pulled_j;
+  {
+    const C jw = (C)(wclass(j) == 1 ? p.jump_axis : p.jump_diag);
+    if (n2.cross > 0) f2_j -= jw;
+    if (n2.cross < 0) f2_j += jw;
+  }
   int rule = p.wall;
   if (rule == kRuleMR && !f3) rule = kRuleCLI;
   if (rule == kRuleQIBB && (q < (C)0.5 ? !f3 : !f2)) rule = kRuleLIBB;
@@ -500,18 +508,18 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
     case kRuleCLI: {
       if (!f2) return own_j;
       const C a = (one - two * q) / (one + two * q);
-      return a * far_value<S, C>(src, st, p, n2, j) - a * own_k + own_j;
+      return a * f2_j - a * own_k + own_j;
     }
     case kRuleLIBB:
       if (q < (C)0.5) {
         if (!f2) return own_j;
-        return (one - two * q) * far_value<S, C>(src, st, p, n2, j) + two * q * own_j;
+        return (one - two * q) * f2_j + two * q * own_j;
       }
       return (one - one / (two * q)) * own_k + own_j / (two * q);
     case kRuleQIBB:
       if (q < (C)0.5)
         return q * (one + two * q) * own_j +
-               (one - (C)4 * q * q) * far_value<S, C>(src, st, p, n2, j) -
+               (one - (C)4 * q * q) * f2_j -
                q * (one - two * q) * far_value<S, C>(src, st, p, n3, j);
       return (two * q - one) / q * own_k + own_j / (q * (two * q + one)) +
              (one - two * q) / (two * q + one) * far_value<S, C>(src, st, p, n2, k);
@@ -542,7 +550,7 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       if (!f2) return own_j;
       const C d = (one + q) * (one + q);
       const C k1 = (one - two * q - two * q * q) / d, k2 = q * q / d;
-      return k1 * far_value<S, C>(src, st, p, n2, j) + k2 * far_value<S, C>(src, st, p, n3, j) -
+      return k1 * f2_j + k2 * far_value<S, C>(src, st, p, n3, j) -
              k1 * own_k - k2 * far_value<S, C>(src, st, p, n2, k) + own_j;
     }
     default:
@@ -608,7 +616,8 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
       if (fl & (1u << k)) {
         if constexpr (WALL == kGEN) {
           // the pulled raw value is the link's wall distance q
-          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1);
+          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1,
+                                                 g[kLat.opp[k]]);
           continue;
         }
         const int j = kLat.opp[k];
@@ -1046,7 +1055,9 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
         const double q = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
-        back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1);
+        const FarNode n2 = far_node(p, x, y, z, k, 1);
+        back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1,
+                                             (double)Storage<S>::to_float(src[j * st + n2.c]));
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
