@@ -976,10 +976,12 @@ NN_API lbm_status nn_conv3d_forward(const void* x, const void* w, const float* b
   const uint16_t* ww = (const uint16_t*)w;
   // spatial tiles where the box and channels allow and the grid is not tiny
   const long long tiles = s.m / (kTZ * kTY * kTX);
-  if (ci % kCC == 0 && bn >= 32 && d % kTZ == 0 && h % kTY == 0 && wd % kTX == 0 &&
+  if (ci % kCC == 0 && d % kTZ == 0 && h % kTY == 0 && wd % kTX == 0 &&
       tiles * ((co + bn - 1) / bn) >= 128) {
     dim3 sgrid((unsigned)tiles, (unsigned)((co + bn - 1) / bn));
-    if (bn == 32)
+    if (bn == 16)
+      conv_fwd_spatial_kernel<16><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+    else if (bn == 32)
       conv_fwd_spatial_kernel<32><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
     else
       conv_fwd_spatial_kernel<64><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);

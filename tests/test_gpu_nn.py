@@ -44,8 +44,10 @@ def _host(t):
 SHAPES = [((2, 6, 4, 8), 8, 8), ((1, 4, 6, 4), 16, 24), ((1, 4, 4, 4), 32, 80),
           ((1, 8, 8, 8), 8, 16),
           # spatially tiled forward path (4 x 8 x 8 tiles, 32-channel chunks):
-          # two batch entries, 64 output channels, and a ragged channel tile
+          # two batch entries, 64 output channels, a ragged channel tile, and 8
+          # outputs (16-column tile, as in the head)
           ((2, 16, 32, 32), 32, 32), ((1, 16, 32, 64), 64, 64), ((1, 8, 32, 64), 96, 96),
+          ((2, 16, 32, 32), 32, 8),
           # spatially tiled weight gradient (at least 256 tiles): two input
           # channel chunks, two output channel tiles, and 16-channel tiles with
           # zero padding (8 inputs as in the first layer, 8 outputs as in the
