@@ -560,7 +560,8 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
 
 
 // One time step for the node (x, y, z), fluid, with flag word fl: pull,
-// wall rule, pressure jump, collision, store.  Returns the pre-collision
+// wall rule, pressure jump, collision, and the 19 values to store (out, in
+// the storage format; the caller stores them).  Returns the pre-collision
 // moments (which the collision conserves) and max_k |g*_k| / w_k of the
 // stored result, for the optional reduction.
 template <typename S, int COLL, int WALL>
@@ -804,7 +805,8 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
 // Each block covers zper consecutive z planes of one cell (zper divides nz),
 // reads that cell's parameters from a device table and skips inactive
 // (converged or stopped) cells.  Block ids of cell b are contiguous, so the
-// partial sums of a cell form one segment.
+// partial sums of a cell form one segment.  p.solid_writes selects which
+// solid cells also store (solid_stores, solid_node).
 
 template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(1024) void batch_step_kernel(
