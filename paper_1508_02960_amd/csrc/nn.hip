@@ -676,6 +676,51 @@ __global__ void cast_bf16_kernel(const float* __restrict__ x, uint16_t* __restri
     y[i] = f2bf(x[i]);
 }
 
+// Four-element forms of the activation, its gradient and the cast (16-byte
+// FP32 words, 8-byte BF16 words), for counts that are multiples of 4 and
+// aligned pointers.
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+  return make_uint2((uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16),
+                    (uint32_t)f2bf(c) | ((uint32_t)f2bf(d) << 16));
+}
+
+__global__ void relu_fwd_vec_kernel(const float4* __restrict__ z, uint2* __restrict__ a,
+                                    long long n4, int relu) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+       i += (long long)gridDim.x * blockDim.x) {
+    float4 v = z[i];
+    if (relu) {
+      v.x = fmaxf(v.x, 0.f);
+      v.y = fmaxf(v.y, 0.f);
+      v.z = fmaxf(v.z, 0.f);
+      v.w = fmaxf(v.w, 0.f);
+    }
+    a[i] = pack_bf16x4(v.x, v.y, v.z, v.w);
+  }
+}
+
+__global__ void relu_bwd_vec_kernel(const float4* __restrict__ da, const uint2* __restrict__ a,
+                                    float4* __restrict__ dz, long long n4) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float4 g = da[i];
+    const uint2 h = a[i];
+    dz[i] = make_float4(bf2f((uint16_t)h.x) > 0.f ? g.x : 0.f,
+                        bf2f((uint16_t)(h.x >> 16)) > 0.f ? g.y : 0.f,
+                        bf2f((uint16_t)h.y) > 0.f ? g.z : 0.f,
+                        bf2f((uint16_t)(h.y >> 16)) > 0.f ? g.w : 0.f);
+  }
+}
+
+__global__ void cast_bf16_vec_kernel(const float4* __restrict__ x, uint2* __restrict__ y,
+                                     long long n4) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float4 v = x[i];
+    y[i] = pack_bf16x4(v.x, v.y, v.z, v.w);
+  }
+}
+
 // 2x2x2 average pooling (fine shape s, coarse = halves), bf16 in/out
 __global__ void pool_fwd_kernel(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, Shape s,
                                 int c) {
@@ -1115,6 +1160,11 @@ NN_API lbm_status nn_bias_grad(const float* dy, float* db, void* ws, size_t ws_b
 NN_API lbm_status nn_activation_forward(const float* z, void* a, long long n, int relu,
                                         void* stream) {
   if (!z || !a || n < 0) return LBM_ERR_INVALID_ARG;
+  if (n % 4 == 0 && aligned16(z) && ((uintptr_t)a & 7) == 0) {
+    relu_fwd_vec_kernel<<<grid_for(n / 4), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)z, (uint2*)a, n / 4, relu);
+    return check_launch();
+  }
   relu_fwd_kernel<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(z, (uint16_t*)a, n, relu);
   return check_launch();
 }
@@ -1122,12 +1172,22 @@ NN_API lbm_status nn_activation_forward(const float* z, void* a, long long n, in
 NN_API lbm_status nn_relu_backward(const float* da, const void* a, float* dz, long long n,
                                    void* stream) {
   if (!da || !a || !dz || n < 0) return LBM_ERR_INVALID_ARG;
+  if (n % 4 == 0 && aligned16(da) && aligned16(dz) && ((uintptr_t)a & 7) == 0) {
+    relu_bwd_vec_kernel<<<grid_for(n / 4), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)da, (const uint2*)a, (float4*)dz, n / 4);
+    return check_launch();
+  }
   relu_bwd_kernel<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(da, (const uint16_t*)a, dz, n);
   return check_launch();
 }
 
 NN_API lbm_status nn_cast_bf16(const float* x, void* y, long long n, void* stream) {
   if (!x || !y || n < 0) return LBM_ERR_INVALID_ARG;
+  if (n % 4 == 0 && aligned16(x) && ((uintptr_t)y & 7) == 0) {
+    cast_bf16_vec_kernel<<<grid_for(n / 4), 256, 0, (hipStream_t)stream>>>(
+        (const float4*)x, (uint2*)y, n / 4);
+    return check_launch();
+  }
   cast_bf16_kernel<<<grid_for(n), 256, 0, (hipStream_t)stream>>>(x, (uint16_t*)y, n);
   return check_launch();
 }

@@ -129,13 +129,17 @@ def test_pool_up_concat_split_relu(ctx, c):
     ga, gb = ctx.f32(5, c), ctx.f32(5, 2 * c)
     assert lib.nn_split_channels(W._p(_f_dev(ctx, g)), W._p(ga), W._p(gb), 5, c, 2 * c, s) == 0
     assert rel(_host(ga), g[:, :c]) < 1e-7 and rel(_host(gb), g[:, c:]) < 1e-7
-    z = rng.standard_normal(1000)
-    act = ctx.bf(1000)
-    assert lib.nn_activation_forward(W._p(_f_dev(ctx, z)), W._p(act), 1000, 1, s) == 0
+    ne = 1000 if c == 8 else 1001  # four-element and element kernels
+    z = rng.standard_normal(ne)
+    act = ctx.bf(ne)
+    assert lib.nn_activation_forward(W._p(_f_dev(ctx, z)), W._p(act), ne, 1, s) == 0
     assert np.array_equal(_host(act), R.bf16(np.maximum(z, 0)))
-    da = rng.standard_normal(1000)
-    dz = ctx.f32(1000)
-    assert lib.nn_relu_backward(W._p(_f_dev(ctx, da)), W._p(act), W._p(dz), 1000, s) == 0
+    cst = ctx.bf(ne)
+    assert lib.nn_cast_bf16(W._p(_f_dev(ctx, z)), W._p(cst), ne, s) == 0
+    assert np.array_equal(_host(cst), R.bf16(z.astype(np.float32).astype(np.float64)))
+    da = rng.standard_normal(ne)
+    dz = ctx.f32(ne)
+    assert lib.nn_relu_backward(W._p(_f_dev(ctx, da)), W._p(act), W._p(dz), ne, s) == 0
     assert np.allclose(_host(dz), np.where(R.bf16(np.maximum(z, 0)) > 0,
                                            da.astype(np.float32), 0))
 
