@@ -207,19 +207,28 @@ lbm_status lbm_macroscopic_device(lbm_domain d, double* fields);
  * scale from the host fields).  Asynchronous on the domain's stream. */
 lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* fields);
 
-/* Superficial mean velocity U[3] = sum over fluid cells of u / ncell, the
- * largest |u| over fluid cells and the total density deviation, reduced in
- * double precision on the device.  Any pointer may be NULL. */
+/* Volume-averaged velocity of eq. (Darcy), taken as the superficial mean
+ * U[3] = sum over fluid cells of u / ncell (the U of eqs. (Darcy),
+ * (Forchheimer) and (AnalyticForce)), the largest |u| over fluid cells and the
+ * total density deviation, reduced in double precision on the device.  Any
+ * pointer may be NULL. */
 lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
                              double* total_drho);
 
-/* Darcy permeability, eq. (Darcy): K_D = nu U_x nx / dp with dp = delta_rho/3;
- * U is the superficial velocity.  Requires delta_rho != 0. */
-lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x);
+/* Darcy permeability, eq. (Darcy): K_D = nu U_x nx / dp with dp = delta_rho/3
+ * (mu = nu for rho0 = 1, pressure gradient dp/nx); U_x is the superficial
+ * velocity (lbm_mean_velocity).  Re_p_per_D = U_x / nu is the pore Reynolds
+ * number of Sec. 1 divided by the length scale, so Re_p = Re_p_per_D * D for
+ * a sphere diameter D (rho = 1).  Any output pointer may be NULL.
+ * Errors: LBM_ERR_STATE when delta_rho is 0 or on a batch. */
+lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x, double* Re_p_per_D);
 
-/* Momentum-exchange force on the solid (host double[3]): sum over wall links
- * (c, j) of e_j (f~_j(c, t) + f_kbar(c, t+1)), f = g + w, with the incoming
- * value given by the wall rule. */
+/* Drag force F_D on the solid, the force of eq. (AnalyticForce)
+ * (C_D = F_D / (6 pi mu U r)), by momentum exchange (host double[3]): the
+ * sum over wall links (c, j) of e_j (f~_j(c, t) + f_kbar(c, t+1)),
+ * f = g + w, with the incoming value given by the wall rule.  At steady state
+ * its x component balances the pressure drop, dp ny nz for a jump plane that
+ * lies in fluid. */
 lbm_status lbm_drag(lbm_domain d, double F[3]);
 
 /* ------------------------------------------------------------------ batches

@@ -368,7 +368,15 @@ __device__ __forceinline__ S g_to_stored(double g, int k, double sigma) {
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 1024;
 constexpr int kRedVals = 8;
-constexpr int kMaxWaves = 8;  // blocks of up to 512 threads
+// Largest workgroups that call block_reduce: the single-domain step
+// (kStepThreads) and the batch step (kBatchThreads, whose shape the autotuner
+// searches up to this size).  block_reduce keeps one LDS slot per wavefront.
+constexpr int kStepThreads = 512;
+constexpr int kBatchThreads = 1024;
+constexpr int kMaxWaves = kBatchThreads / 64;
+static_assert(kMaxWaves * 64 >= kStepThreads && kMaxWaves * 64 >= kBatchThreads &&
+                  kMaxWaves * 64 >= kRedThreads,
+              "block_reduce needs an LDS slot for every wavefront of the largest block");
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -753,7 +761,7 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[k
 // count) to partials[block].  NT selects non-temporal stores (FP32 and
 // FP64 storage only).
 template <typename S, int COLL, int WALL, bool RED, bool NT>
-__global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
+__global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict__ src,
                                                    S* __restrict__ dst,
                                                    const uint32_t* __restrict__ flags,
                                                    const StepParams p,
@@ -809,7 +817,7 @@ __global__ __launch_bounds__(512) void step_kernel(const S* __restrict__ src,
 // solid cells also store (solid_stores, solid_node).
 
 template <typename S, int COLL, int WALL, bool RED, bool NT>
-__global__ __launch_bounds__(1024) void batch_step_kernel(
+__global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const uint32_t* __restrict__ flags,
     const StepParams* __restrict__ cells, const int* __restrict__ active, int nz_cell,
     long long cell_size, int zper, double* __restrict__ partials) {

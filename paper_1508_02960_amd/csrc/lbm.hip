@@ -345,7 +345,7 @@ lbm_status enqueue_steps(lbm_domain d, int64_t n) {
 // ---- batches
 
 dim3 batch_block(lbm_domain d) {
-  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
+  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
   return dim3(bx, d->bby, 1);
 }
 dim3 batch_grid(lbm_domain d) {
@@ -1134,8 +1134,9 @@ LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_spee
 }
 
 // eq. (Darcy): K_D = mu U / |grad P| with mu = nu (rho0 = 1), |grad P| = dp/nx,
-// dp = delta_rho / 3.
-LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x) {
+// dp = delta_rho / 3; Re_p / D = U / nu (Sec. 1, rho = 1).
+LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x,
+                                    double* Re_p_per_D) {
   lbm_status st = check_ready(d);
   if (st != LBM_OK) return st;
   if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
@@ -1146,6 +1147,7 @@ LBM_API lbm_status lbm_permeability(lbm_domain d, double* K_D, double* U_x) {
   const double dp = d->p.delta_rho / 3.0;
   if (K_D) *K_D = d->nu * U[0] * d->geo.nx / dp;
   if (U_x) *U_x = U[0];
+  if (Re_p_per_D) *Re_p_per_D = U[0] / d->nu;
   return LBM_OK;
 }
 
@@ -1262,7 +1264,7 @@ LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
   d->nu = (cells[0].tau - 0.5) / 3.0;
   d->omega_p = 1.0 / cells[0].tau;
   d->omega_m = d->omega_p;
-  d->bby = std::max(1, 256 / std::min(1024, ((p.nx + 63) / 64) * 64));
+  d->bby = std::max(1, 256 / std::min(kBatchThreads, ((p.nx + 63) / 64) * 64));
   d->zper = 1;
   layout(d);
   choose_sigma(d, 0.0);
@@ -1296,8 +1298,8 @@ LBM_API lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64
 
 LBM_API lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper) {
   if (!d || !d->batch) return LBM_ERR_INVALID_ARG;
-  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
-  if (by < 1 || bx * by > 1024 || zper < 1 || d->geo.nz_cell % zper != 0)
+  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
+  if (by < 1 || bx * by > kBatchThreads || zper < 1 || d->geo.nz_cell % zper != 0)
     return fail(d, LBM_ERR_INVALID_ARG, "by*row width must be <= 1024 and zper must divide nz");
   d->bby = by;
   d->zper = zper;
@@ -1322,7 +1324,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
   if (st != LBM_OK) return st;
   if (!d->batch) return fail(d, LBM_ERR_STATE, "autotune applies to batches");
   if (steps < 1) return fail(d, LBM_ERR_INVALID_ARG, "steps must be >= 1");
-  const int bx = std::min(1024, ((d->geo.nx + 63) / 64) * 64);
+  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
   hipEvent_t e0, e1;
   HIP_OK(d, hipEventCreate(&e0));
   HIP_OK(d, hipEventCreate(&e1));
@@ -1332,7 +1334,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
     d->solid_writes = mode;
     st = upload_cell_params(d);
     if (st != LBM_OK) break;
-    for (int by = 1; by * bx <= 1024 && by <= d->geo.ny; by *= 2) {
+    for (int by = 1; by * bx <= kBatchThreads && by <= d->geo.ny; by *= 2) {
       for (int zp = 1; zp <= 8 && zp <= d->geo.nz_cell; zp *= 2) {
         if (d->geo.nz_cell % zp) continue;
         d->bby = by;

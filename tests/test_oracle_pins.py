@@ -171,6 +171,77 @@ def test_mrt_rates_follow_pan_and_khirevich(orc):
         assert abs((1 / s_nu - 0.5) * (1 / kin[0] - 0.5) - 3 / 16) < 1e-14
 
 
+
+# Shear waves: a pin of which moments carry the viscosity.  A small-amplitude
+# wave u = A e sin(k.x) with e perpendicular to k decays as exp(-nu |k|^2 t)
+# in the Navier-Stokes limit (Sec. 2: nu = (1/s_nu - 1/2)/3 with s_nu = 1/tau
+# on the stress moments of eq. (MRT)).  A wave along a lattice axis probes an
+# off-diagonal stress moment (p_xy, p_yz or p_xz); a wave along a face
+# diagonal with e along the other diagonal probes a normal-stress difference
+# (p_xx - p_yy etc., i.e. the moments 3p_xx and p_ww), so each of the five
+# stress rows of M is exercised with its relaxation rate.  The lattice adds
+# an O(|k|^2) correction to the decay rate, so the measured viscosity is
+# extrapolated from two wavelengths (second order: the errors fall 4x per
+# doubling).
+
+_SHEAR_WAVES = {
+    # name: (box axes holding the wave, wave vector k / (2 pi / L), velocity direction)
+    "xy": ((1, 2), (0, 1, 0), (1, 0, 0)),       # u_x(y): p_xy
+    "yz": ((0, 1), (0, 0, 1), (0, 1, 0)),       # u_y(z): p_yz
+    "xz": ((0, 2), (1, 0, 0), (0, 0, 1)),       # u_z(x): p_xz
+    "xx-yy": ((1, 2), (1, 1, 0), (1, -1, 0)),   # normal stresses, xy plane
+    "yy-zz": ((0, 1), (0, 1, 1), (0, 1, -1)),   # yz plane
+    "xx-zz": ((0, 2), (1, 0, 1), (1, 0, -1)),   # xz plane
+}
+
+
+def _shear_wave_viscosity(orc, L, wave, collision, tau, t1=20, t2=220):
+    """Viscosity read from the decay of the wave between steps t1 and t2 in
+    a periodic box that is L cells along the two axes the wave varies in and
+    one cell along the third (the flow is uniform along it)."""
+    axes, kv, ev = _SHEAR_WAVES[wave]
+    shape = [1, 1, 1]  # (nz, ny, nx)
+    for a in axes:
+        shape[a] = L
+    shape = tuple(shape)
+    z, y, x = np.meshgrid(*(np.arange(n) for n in shape), indexing="ij")
+    phase = 2 * np.pi * (kv[0] * x + kv[1] * y + kv[2] * z) / L
+    e = np.array(ev, float) / np.linalg.norm(ev)
+    k2 = (2 * np.pi / L) ** 2 * float(np.dot(kv, kv))
+    s = np.sin(phase)
+    o = orc.Oracle(shape, tau=tau, magic=3 / 16, collision=collision,
+                   mask=np.zeros(shape, np.uint8))
+    o.init(u0=1e-4 * e[:, None, None, None] * s[None])
+
+    def amplitude():
+        _, u = o.macroscopic()
+        return 2 * np.mean(np.tensordot(e, u, axes=1) * s)
+
+    o.step(t1)
+    a1 = amplitude()
+    o.step(t2 - t1)
+    a2 = amplitude()
+    return np.log(a1 / a2) / (t2 - t1) / k2
+
+
+@pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
+@pytest.mark.parametrize("wave", sorted(_SHEAR_WAVES))
+def test_shear_wave_decay_gives_viscosity(orc, collision, wave):
+    """Every stress moment relaxes with s_nu = 1/tau (Sec. 2.1): the decay of
+    shear waves of every orientation gives nu = (tau - 1/2)/3.  A stress row
+    of M relaxed at another rate (for instance rows 3p_xx and 3pi_xx swapped,
+    which puts 3p_xx at Pan's s_zeta) changes the normal-stress waves by
+    20-1300 %; the discretisation error at L = 32 is below 2 %."""
+    for tau in (0.6, 0.8, 1.4):
+        nu = (tau - 0.5) / 3
+        n32 = _shear_wave_viscosity(orc, 32, wave, collision, tau)
+        n64 = _shear_wave_viscosity(orc, 64, wave, collision, tau)
+        assert abs(n64 / nu - 1) < 6e-3, (tau, n64 / nu - 1)
+        # second order in |k|: Richardson extrapolation removes the lattice term
+        ext = (4 * n64 - n32) / 3
+        assert abs(ext / nu - 1) < 2e-4, (tau, ext / nu - 1)
+
+
 # ---------------------------------------------------------------- geometry
 
 def _numpy_mask(shape, spheres):
@@ -345,7 +416,7 @@ def test_no_solid_acceleration_is_exact(orc):
             assert abs(U[1]) < 1e-18 and abs(U[2]) < 1e-18
 
 
-def _poiseuille(orc, H, tau, lam, wall="sbb", q=0.5, nx=3):
+def _poiseuille(orc, H, tau, lam, wall="sbb", q=0.5, nx=3, collision="trt"):
     """Plane channel: solid rows y = 0 and y = H+1, fluid y = 1..H, periodic
     in x and z, driven by the jump.  Links to either wall get wall distance q."""
     shape = (1, H + 2, nx)
@@ -353,7 +424,7 @@ def _poiseuille(orc, H, tau, lam, wall="sbb", q=0.5, nx=3):
     mask[:, 0, :] = 1
     mask[:, H + 1, :] = 1
     drho = 1e-5
-    o = orc.Oracle(shape, tau=tau, magic=lam, delta_rho=drho, collision="trt", wall=wall,
+    o = orc.Oracle(shape, tau=tau, magic=lam, delta_rho=drho, collision=collision, wall=wall,
                    mask=mask)
     o.Q[o.Q >= 0] = q
     o.init()
@@ -374,6 +445,24 @@ def test_poiseuille_exact_with_magic_3_16(orc, tau):
     exact = G / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
     err = np.max(np.abs(u[1:H + 1] - exact[1:H + 1])) / exact.max()
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_poiseuille_exact_with_mrt(orc, tau):
+    """Sec. 2.1: Pan's kinetic rate s_zeta = 8(2 - s_nu)/(8 - s_nu) makes
+    (1/s_nu - 1/2)(1/s_zeta - 1/2) = 3/16, the combination that puts
+    bounce-back walls exactly half-way, so the MRT channel profile is the
+    parabola to rounding; SRT (no free odd rate) is the negative control."""
+    H = 8
+    nu = (tau - 0.5) / 3
+    y = np.arange(H + 2)
+    errs = {}
+    for coll in ("mrt", "srt"):
+        _, u, G = _poiseuille(orc, H, tau, 3 / 16, collision=coll)
+        exact = G / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+        errs[coll] = np.max(np.abs(u[1:H + 1] - exact[1:H + 1])) / exact.max()
+    assert errs["mrt"] < 1e-10
+    assert errs["srt"] > 1e-3
 
 
 def test_poiseuille_magic_quarter_is_not_exact(orc):
