@@ -269,17 +269,18 @@ lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks, const lbm_sph
 lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64_t* steps,
                              double* residual, int32_t* status);
 
-/* Launch shape of the batch step: rows of cells per workgroup (by; the
- * workgroup spans a full x row, by rows, up to 1024 threads) and z planes
- * per workgroup (zper, a divisor of nz). */
-lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper);
+/* Launch shape of the batch step: wavefronts per workgroup (waves, 1..16;
+ * each wavefront takes one tile of 64 cells of a z plane, consecutive tiles
+ * per workgroup) and z planes per workgroup (zper, a divisor of nz).
+ * LBM_ERR_INVALID_ARG otherwise. */
+lbm_status lbm_batch_set_shape(lbm_domain d, int32_t waves, int32_t zper);
 
-/* Time every admissible (by, zper) and solid-write mode (lbm_set_solid_writes)
+/* Time every admissible (waves, zper) and solid-write mode (lbm_set_solid_writes)
  * over `steps` steps each (after two warm-up steps) with HIP events on the
  * domain's stream, keep the fastest, and return the shape with its time per
  * step in ms (the mode is read with lbm_get_solid_writes).  The state is
  * reset to rest afterwards. */
-lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by, int32_t* zper,
+lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* waves, int32_t* zper,
                               double* ms_per_step);
 
 /* Which solid cells a batch step writes; an implementation choice with no
@@ -288,7 +289,7 @@ lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by, int32_t*
  * a direction plane, the fluid cells write only part of it; solid cells
  * sharing the line can complete it (zeros, and copies of their wall-link
  * slots).  mode 0: fluid cells only (default); 1: also solid cells whose
- * 64-cell wavefront along x holds a fluid cell; 2: also solid cells whose
+ * 64-cell tile (wavefront) holds a fluid cell; 2: also solid cells whose
  * line holds a fluid cell.  lbm_batch_autotune picks the fastest.  Invalid
  * mode: LBM_ERR_INVALID_ARG; mode 1 or 2 on a single domain (whose step
  * always writes fluid cells only): LBM_ERR_STATE. */
@@ -303,6 +304,33 @@ lbm_status lbm_synchronize(lbm_domain d);
 
 /* Release host memory of the domain (the workspace stays the caller's). */
 lbm_status lbm_destroy(lbm_domain d);
+
+/* ---------------------------------------------------------------- probes
+ * Attainable-bandwidth probes, a measurement aid (not an operation of the
+ * method): plain streaming kernels of known byte counts that bound what the
+ * step kernel can reach on the GPU at hand and calibrate HBM byte counters.
+ * Asynchronous on `stream` (a hipStream_t or NULL); the caller times them,
+ * e.g. with events on that stream.  Buffers are caller-owned device memory,
+ * 16-byte aligned.
+ *   LBM_PROBE_READ     reads n bytes of src (dst: >= 16 bytes, written only
+ *                      if the data sum to a sentinel value, i.e. never for
+ *                      ordinary data); n a positive multiple of 16
+ *   LBM_PROBE_WRITE    writes n bytes to dst (src unused)
+ *   LBM_PROBE_COPY     copies n bytes from src to dst
+ *   LBM_PROBE_GATHER19 the step's pull pattern on an all-fluid periodic cube
+ *                      of edge n (multiple of 8, at most 1024): src and dst
+ *                      hold 19 FP32 planes of n^3 values in 8 x 8 tiles;
+ *                      reads and writes 2 * 76 n^3 bytes
+ * Errors: LBM_ERR_INVALID_ARG for an unknown kind, a bad size, NULL or
+ * misaligned buffers; LBM_ERR_DEVICE if the launch fails. */
+typedef enum {
+  LBM_PROBE_READ = 0,
+  LBM_PROBE_WRITE = 1,
+  LBM_PROBE_COPY = 2,
+  LBM_PROBE_GATHER19 = 3
+} lbm_probe_kind;
+lbm_status lbm_bandwidth_probe(int32_t kind, const void* src, void* dst, int64_t n,
+                               void* stream);
 
 const char* lbm_status_string(lbm_status s);
 /* Last error message of the domain ("" if none); NULL domain: last create error. */

@@ -7,5 +7,5 @@ may import this package.  It loads ``liblbm_oracle.so`` built from
 from .oracle import (  # noqa: F401
     COLLISIONS, WALLS, Oracle, build, lattice, mrt_matrix, mrt_rates,
     trt_omega_minus, equilibrium, collide, collide_mrt_rates, voxelise,
-    link_q, wall_q, library_path,
+    link_q, wall_q, library_path, set_threads,
 )

@@ -24,6 +24,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* D3Q19 velocity set (Sec. 2: 19 discrete velocities e_k). */
 static const int32_t VEL[19][3] = {
@@ -500,12 +503,23 @@ double orc_wall_value(const orc_params* p, const uint8_t* mask, const double* Q,
   return wall_value(p, mask, Q, g, x, y, z, k);
 }
 
+/* Threads for the time step (OpenMP builds only; 1 by default).  Nodes are
+ * updated independently, so the result does not depend on the count. */
+static int n_threads = 1;
+void orc_set_threads(int32_t n) { n_threads = n > 0 ? n : 1; }
+
 /* Fused step in the paper's order (Sec. 2: first streaming, then collision):
  * pull every population into the node (eq. (streaming) read backwards),
- * replace those whose source is solid by the wall rule, then collide. */
+ * replace those whose source is solid by the wall rule, then collide.  Each
+ * node reads the old state only and writes its own values, so z planes may be
+ * updated by different threads. */
 void orc_step(const orc_params* p, const uint8_t* mask, const double* Q,
               const double* g, double* gout) {
   int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+  ensure_tables();
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+#endif
   for (int z = 0; z < p->nz; ++z)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {

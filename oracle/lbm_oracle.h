@@ -90,6 +90,10 @@ void orc_init(const orc_params* p, const uint8_t* mask, const double* drho0,
 double orc_wall_value(const orc_params* p, const uint8_t* mask, const double* Q,
                       const double* g, int32_t x, int32_t y, int32_t z, int32_t k);
 
+/* Threads used by orc_step in an OpenMP build (default 1); the result is
+ * the same for any count. */
+void orc_set_threads(int32_t n);
+
 /* One fused stream-then-collide step: gout <- step(g). */
 void orc_step(const orc_params* p, const uint8_t* mask, const double* Q,
               const double* g, double* gout);

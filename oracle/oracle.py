@@ -28,7 +28,7 @@ def library_path() -> str:
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no contraction of a*b+c)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
@@ -74,6 +74,7 @@ def _load():
             "orc_permeability": (d, [P(_Params), d]),
             "orc_run_to_residual": (i32, [P(_Params), vp, vp, vp, vp, d, i64, i64,
                                           P(i64), P(d)]),
+            "orc_set_threads": (None, [i32]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(lib, name)
@@ -81,6 +82,12 @@ def _load():
             f.argtypes = args
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's time step (1 unless set; results do not
+    depend on it)."""
+    _load().orc_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray | None):

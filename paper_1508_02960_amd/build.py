@@ -4,18 +4,20 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
+OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["lbm.hip", "geometry.cpp", "nn.hip"]
+SOURCES = ["lbm.hip", "geometry.cpp", "nn.hip", "ceiling.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -28,10 +30,22 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source of the package into liblbm.so."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile every HIP/C++ source of the package (one process per source)
+    and link liblbm.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, s + ".o") for s in SOURCES]
+
+    def compile_one(i: int) -> None:
+        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", "-o", objs[i],
+               os.path.join(CSRC, SOURCES[i])]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        subprocess.run(cmd, check=True)
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        list(ex.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

@@ -2,14 +2,20 @@
 //
 // Data layout in HBM: two population buffers (A: current post-collision
 // state, B: next), each 19 direction planes of `stride` elements, the plane
-// of direction k holding g_k = f_k - w_k for every cell c = x + nx*(y + ny*z).
-// A uint32 flag word per cell marks solid cells and the directions whose pull
-// source is solid.  For such a wall link the otherwise unused slot of the
-// solid source node in plane k holds the CLI coefficient a = (1-2q)/(1+2q)
-// (0 for fallback links), written once at bind time into both buffers.  In
-// batches, solid cells next to fluid cells may copy their link slots and
-// write zeros elsewhere (whole-line writes, solid_stores); otherwise solid
-// cells are not written, so the slots persist either way.
+// of direction k holding g_k = f_k - w_k of every cell.  Cells are stored in
+// tiled order (Tiling): each z plane is cut into tiles of 64 cells, one
+// wavefront each (8 x 8 cells for 4- and 8-byte storage, 16 x 4 for 2-byte
+// storage), so a 128-byte line of a plane covers a compact patch of cells
+// rather than a stretch of one row; where sphere surfaces cut the lines,
+// fewer of them are fetched for a few fluid cells.  A uint8 class per cell
+// says whether the cell is solid and whether it has wall links; the uint32
+// flag word of a cell with links marks the directions whose pull source is
+// solid.  For such a wall link the otherwise unused slot of the solid source
+// node in plane k holds the CLI coefficient a = (1-2q)/(1+2q) (0 for
+// fallback links), written once at bind time into both buffers.  In batches,
+// solid cells next to fluid cells may copy their link slots and write zeros
+// elsewhere (whole-line writes, solid_stores); otherwise solid cells are not
+// written, so the slots persist either way.
 //
 // The step is a pull scheme: each fluid cell gathers its 19 incoming values
 // from its neighbours (one read per element of A), applies the wall rule and
@@ -32,7 +38,47 @@ enum { kSBB = 0, kCLI = 1, kGEN = 2 };
 // run-time rule numbers (lbm_wall)
 enum { kRuleSBB = 0, kRuleCLI = 1, kRuleLIBB = 2, kRuleQIBB = 3, kRuleIEBB = 4, kRuleMR = 5 };
 
+// Tiled cell order.  A z plane of nx x ny cells is padded to whole tiles of
+// 2^tw_log2 x 2^th_log2 = 64 cells; tiles follow each other in x, then y;
+// cells inside a tile in x, then y; planes follow in z.  The address of
+// (x, y, z) splits into independent x, y and z parts, so neighbour addresses
+// are sums of three precomputed offsets.  Padding cells are marked solid and
+// never read as a neighbour (the periodic wrap uses nx and ny).
+struct Tiling {
+  int nx, ny;            // box edge in x and y (cells)
+  int tw_log2, th_log2;  // tile width and height, log2 (sum 6)
+  int ntx;               // tiles per tile row (padded nx / tile width)
+  int nty;               // tile rows per plane
+  int plane;             // cells per z plane including padding: ntx * nty * 64
+  __host__ __device__ int xpart(int x) const {
+    return ((x >> tw_log2) << 6) | (x & ((1 << tw_log2) - 1));
+  }
+  __host__ __device__ int ypart(int y) const {
+    return (y >> th_log2) * (ntx << 6) + ((y & ((1 << th_log2) - 1)) << tw_log2);
+  }
+  __host__ __device__ int at(int x, int y, int z) const { return xpart(x) + ypart(y) + z * plane; }
+  // inverse of at() (padding cells give x >= nx or y >= ny)
+  __host__ __device__ void coords(int a, int& x, int& y, int& z) const {
+    z = a / plane;
+    const int r = a - z * plane;
+    const int t = r >> 6, l = r & 63;
+    x = ((t % ntx) << tw_log2) + (l & ((1 << tw_log2) - 1));
+    y = ((t / ntx) << th_log2) + (l >> tw_log2);
+  }
+  // address of the cell with row-major index c = x + nx (y + ny z)
+  __host__ __device__ int from_linear(long long c) const {
+    const int x = (int)(c % nx);
+    const long long r = c / nx;
+    return at(x, (int)(r % ny), (int)(r / ny));
+  }
+};
+
+// Cell classes (one byte per cell, tiled order).
+constexpr uint8_t kClsSolid = 1;  // solid (or padding) cell
+constexpr uint8_t kClsLinks = 2;  // the cell's flag word has link bits
+
 struct StepParams {
+  Tiling t;
   int nx, ny, nz;
   long long stride;   // elements between direction planes
   double jump_axis;   // w_axis * delta_rho
@@ -369,9 +415,10 @@ constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 1024;
 constexpr int kRedVals = 8;
 // Largest workgroups that call block_reduce: the single-domain step
-// (kStepThreads) and the batch step (kBatchThreads, whose shape the autotuner
-// searches up to this size).  block_reduce keeps one LDS slot per wavefront.
-constexpr int kStepThreads = 512;
+// (kStepThreads, up to 16 wavefronts of one tile each) and the batch step
+// (kBatchThreads, whose shape the autotuner searches up to this size).
+// block_reduce keeps one LDS slot per wavefront.
+constexpr int kStepThreads = 1024;
 constexpr int kBatchThreads = 1024;
 constexpr int kMaxWaves = kBatchThreads / 64;
 static_assert(kMaxWaves * 64 >= kStepThreads && kMaxWaves * 64 >= kBatchThreads &&
@@ -414,12 +461,12 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&kind)[
 
 // ---------------------------------------------------------------- the step
 
-// Flat cell index of the node at (x + dx, y + dy, z + dz) given the wrapped
-// neighbour coordinates of the thread's node.
+// Address of the node at (x + dx, y + dy, z + dz) given the tiled-address
+// parts of the thread's wrapped neighbour coordinates.
 struct Nbr {
-  int xs[3];  // x - 1, x, x + 1 (wrapped)
-  int ys[3];  // row offsets of y - 1, y, y + 1 (wrapped) times nx
-  int zs[3];  // plane offsets of z - 1, z, z + 1 (wrapped) times nx*ny
+  int xs[3];  // x parts of x - 1, x, x + 1 (wrapped)
+  int ys[3];  // y parts of y - 1, y, y + 1 (wrapped)
+  int zs[3];  // plane offsets of z - 1, z, z + 1 (wrapped)
   __device__ __forceinline__ int at(int dx, int dy, int dz) const {
     return xs[dx + 1] + ys[dy + 1] + zs[dz + 1];
   }
@@ -441,8 +488,8 @@ __device__ __forceinline__ FarNode far_node(const StepParams& p, int x, int y, i
   const int X = x + m * kLat.ex[k];
   FarNode f;
   f.cross = X >= p.nx ? 1 : (X < 0 ? -1 : 0);
-  f.c = wrap_into(X, p.nx) + p.nx * (wrap_into(y + m * kLat.ey[k], p.ny) +
-                                     p.ny * wrap_into(z + m * kLat.ez[k], p.nz));
+  f.c = p.t.at(wrap_into(X, p.nx), wrap_into(y + m * kLat.ey[k], p.ny),
+               wrap_into(z + m * kLat.ez[k], p.nz));
   return f;
 }
 
@@ -579,14 +626,14 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
                                             uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
   using St = Storage<S>;
-  const int nx = p.nx, plane = p.nx * p.ny;
+  const int nx = p.nx, plane = p.t.plane;
   Nbr n;
-  n.xs[0] = x == 0 ? nx - 1 : x - 1;
-  n.xs[1] = x;
-  n.xs[2] = x == nx - 1 ? 0 : x + 1;
-  n.ys[0] = (y == 0 ? p.ny - 1 : y - 1) * nx;
-  n.ys[1] = y * nx;
-  n.ys[2] = (y == p.ny - 1 ? 0 : y + 1) * nx;
+  n.xs[0] = p.t.xpart(x == 0 ? nx - 1 : x - 1);
+  n.xs[1] = p.t.xpart(x);
+  n.xs[2] = p.t.xpart(x == nx - 1 ? 0 : x + 1);
+  n.ys[0] = p.t.ypart(y == 0 ? p.ny - 1 : y - 1);
+  n.ys[1] = p.t.ypart(y);
+  n.ys[2] = p.t.ypart(y == p.ny - 1 ? 0 : y + 1);
   n.zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
   n.zs[1] = z * plane;
   n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
@@ -740,55 +787,90 @@ __device__ __forceinline__ bool solid_stores(int mode, bool solid, unsigned long
   }
 }
 
-// Store a node's 19 values; NT selects non-temporal stores (FP32 and FP64
-// storage only: the new state is not read again within this step).
+// Store a node's 19 values; NT selects non-temporal stores (the new state is
+// not read again within this step).
+template <typename S>
+__device__ __forceinline__ void nontemporal_store(S v, S* p) {
+  if constexpr (sizeof(S) == 2)  // the 16-bit formats as their bit patterns
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+  else
+    __builtin_nontemporal_store(v, p);
+}
+
 template <typename S, bool NT>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[kQ], long long st,
                                            int c) {
 #pragma unroll
   for (int k = 0; k < kQ; ++k) {
     if constexpr (NT)
-      __builtin_nontemporal_store(out[k], &dst[k * st + c]);
+      nontemporal_store(out[k], &dst[k * st + c]);
     else
       dst[k * st + c] = out[k];
   }
 }
 
-// The fused stream-and-collide step over the box.  Block (bx, by) covers
-// full x rows (bx >= nx, up to 512) so that the +-1 shifted row reads of a
-// row stay inside one workgroup.  With RED the block also writes FP64
-// partial sums of the state it produced (u, drho, max |u|^2, non-finite
-// count) to partials[block].  NT selects non-temporal stores (FP32 and
-// FP64 storage only).
+// Cell of this thread in plane z: wavefront threadIdx.y of the block takes
+// tile blockIdx.x * blockDim.y + threadIdx.y of the plane (tiles in row-major
+// order), lane threadIdx.x its cell in the tile, so the lanes of a wavefront
+// hold 64 consecutive addresses.  inside is false for padding cells and for
+// tiles past the end of the plane (c must not be used then).
+struct TileCell {
+  int x, y, c;
+  bool inside;
+};
+__device__ __forceinline__ TileCell tile_cell(const Tiling& t, int z) {
+  const int tile = blockIdx.x * blockDim.y + threadIdx.y;
+  const int l = threadIdx.x;
+  const int tx = tile % t.ntx, ty = tile / t.ntx;
+  TileCell r;
+  r.x = (tx << t.tw_log2) + (l & ((1 << t.tw_log2) - 1));
+  r.y = (ty << t.th_log2) + (l >> t.tw_log2);
+  r.inside = ty < t.nty && r.x < t.nx && r.y < t.ny;
+  r.c = (tile << 6) + l + z * t.plane;
+  return r;
+}
+
+// Flag word of a cell from its class byte: only cells with wall links (or
+// link slots, for solid cells) read the word.
+__device__ __forceinline__ uint32_t flag_word(uint8_t k, const uint32_t* __restrict__ flags, int c) {
+  if (k & kClsLinks) return flags[c];
+  return (k & kClsSolid) ? kSolid : 0u;
+}
+
+// The fused stream-and-collide step over the box.  A block of blockDim.y
+// wavefronts covers that many consecutive tiles of one z plane; with 8 x 8
+// tiles and 16 wavefronts it spans 128 x 8 cells, so most of the lines that
+// the +-1 shifted pulls share with neighbouring tiles are read by the same
+// workgroup.  With RED the block also writes FP64 partial sums of the state
+// it produced (u, drho, max |u|^2, non-finite count) to partials[block].  NT
+// selects non-temporal stores (the new state is not read again in the step).
 template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict__ src,
-                                                   S* __restrict__ dst,
-                                                   const uint32_t* __restrict__ flags,
-                                                   const StepParams p,
-                                                   double* __restrict__ partials) {
+                                                            S* __restrict__ dst,
+                                                            const uint8_t* __restrict__ cls,
+                                                            const uint32_t* __restrict__ flags,
+                                                            const StepParams p,
+                                                            double* __restrict__ partials) {
   using C = typename ComputeOf<S>::type;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
-  const bool inside = x < p.nx && y < p.ny;
-  const int c = x + p.nx * y + p.nx * p.ny * z;
+  const TileCell tc = tile_cell(p.t, z);
   const long long st = p.stride;
+  const uint8_t k = tc.inside ? cls[tc.c] : kClsSolid;
   if constexpr (!RED) {
-    if (!inside) return;
-    const uint32_t fl = flags[c];
-    if (fl & kSolid) return;
+    if (k & kClsSolid) return;
+    const uint32_t fl = flag_word(k, flags, tc.c);
     S out[kQ];
     C mom[5];
-    update_node<S, COLL, WALL>(src, out, flags, p, x, y, z, c, fl, mom);
-    store_node<S, NT>(dst, out, st, c);
+    update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
+    store_node<S, NT>(dst, out, st, tc.c);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint32_t fl = inside ? flags[c] : kSolid;
-    if (!(fl & kSolid)) {
+    if (!(k & kClsSolid)) {
+      const uint32_t fl = flag_word(k, flags, tc.c);
       S out[kQ];
       C mom[5];
-      update_node<S, COLL, WALL>(src, out, flags, p, x, y, z, c, fl, mom);
-      store_node<S, NT>(dst, out, st, c);
+      update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
+      store_node<S, NT>(dst, out, st, tc.c);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
       v[0] = ux;
@@ -802,43 +884,45 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
       v[6] = isfinite((double)mom[4]) ? (double)mom[4] : 0.0;
     }
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
-    const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.z;
     block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
   }
 }
 
 // ------------------------------------------------------------ batches of cells
 // B independent periodic cells of nx x ny x nz are stacked along z (cell b
-// occupies cells [b*cell_size, (b+1)*cell_size) of every direction plane).
-// Each block covers zper consecutive z planes of one cell (zper divides nz),
-// reads that cell's parameters from a device table and skips inactive
+// occupies addresses [b*cell_size, (b+1)*cell_size) of every direction plane,
+// cell_size = nz planes of the cell's tiling).  Each block covers blockDim.y
+// consecutive tiles of zper consecutive z planes of one cell (zper divides
+// nz), reads that cell's parameters from a device table and skips inactive
 // (converged or stopped) cells.  Block ids of cell b are contiguous, so the
 // partial sums of a cell form one segment.  p.solid_writes selects which
 // solid cells also store (solid_stores, solid_node).
 
 template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
-    const S* __restrict__ src, S* __restrict__ dst, const uint32_t* __restrict__ flags,
-    const StepParams* __restrict__ cells, const int* __restrict__ active, int nz_cell,
-    long long cell_size, int zper, double* __restrict__ partials) {
+    const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ cls,
+    const uint32_t* __restrict__ flags, const StepParams* __restrict__ cells,
+    const int* __restrict__ active, int nz_cell, long long cell_size, int zper,
+    double* __restrict__ partials) {
   using C = typename ComputeOf<S>::type;
   const int zz0 = blockIdx.z * zper;
   const int b = zz0 / nz_cell;
   if (!active[b]) return;
   const StepParams p = cells[b];
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const bool inside = x < p.nx && y < p.ny;
   const long long off = (long long)b * cell_size;
   const S* s = src + off;
   S* d = dst + off;
+  const uint8_t* cl = cls + off;
   const uint32_t* f = flags + off;
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = 0; i < zper; ++i) {
     const int z = zz0 + i - b * nz_cell;
-    const int c = x + p.nx * y + p.nx * p.ny * z;
-    const uint32_t fl = inside ? f[c] : kSolid;
-    const bool solid = fl & kSolid;
+    const TileCell tc = tile_cell(p.t, z);
+    const int c = tc.c;
+    const uint8_t k = tc.inside ? cl[c] : kClsSolid;
+    const bool solid = k & kClsSolid;
+    const uint32_t fl = tc.inside ? flag_word(k, f, c) : kSolid;
     const unsigned long long fluid = __ballot(!solid);
     if (!solid_stores<S>(p.solid_writes, solid, fluid)) continue;
     S out[kQ];
@@ -846,8 +930,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     if (solid)
       solid_node<S>(s, out, p.stride, c, fl);
     else
-      update_node<S, COLL, WALL>(s, out, f, p, x, y, z, c, fl, mom);
-    if (inside) store_node<S, NT>(d, out, p.stride, c);
+      update_node<S, COLL, WALL>(s, out, f, p, tc.x, tc.y, z, c, fl, mom);
+    if (tc.inside) store_node<S, NT>(d, out, p.stride, c);
     if (solid) continue;
     if constexpr (RED) {
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
@@ -864,7 +948,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
   }
   if constexpr (RED) {
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
-    const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    const long long blk = blockIdx.x + (long long)gridDim.x * blockIdx.z;
     block_reduce<kRedVals>(v, kind, partials + blk * kRedVals);
   }
 }
@@ -1003,11 +1087,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const doub
 template <typename S>
 __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __restrict__ src,
                                                                    const uint32_t* __restrict__ flags,
-                                                                   long long stride, int ncell,
+                                                                   long long stride, int naddr,
                                                                    double sigma,
                                                                    double* __restrict__ partials) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long c = blockIdx.x * kRedThreads + threadIdx.x; c < ncell;
+  for (long long c = blockIdx.x * kRedThreads + threadIdx.x; c < naddr;
        c += (long long)gridDim.x * kRedThreads) {
     if (flags[c] & kSolid) continue;
     double g[kQ];
@@ -1031,21 +1115,22 @@ __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __re
 }
 
 // Momentum-exchange force over the wall links (f = g + w), same wall rule as
-// the step kernel.
+// the step kernel.  Threads walk the tiled addresses; padding cells are solid.
 template <typename S, int WALL>
 __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__ src,
                                                            const uint32_t* __restrict__ flags,
                                                            const StepParams p,
                                                            double* __restrict__ partials) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int ncell = p.nx * p.ny * p.nz;
+  const int naddr = p.t.plane * p.nz;
   const long long st = p.stride;
-  for (long long cc = blockIdx.x * kRedThreads + threadIdx.x; cc < ncell;
+  for (long long cc = blockIdx.x * kRedThreads + threadIdx.x; cc < naddr;
        cc += (long long)gridDim.x * kRedThreads) {
     const int c = (int)cc;
     const uint32_t fl = flags[c];
     if ((fl & kSolid) || !(fl & kLinkMask)) continue;
-    const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / (p.nx * p.ny);
+    int x, y, z;
+    p.t.coords(c, x, y, z);
     double m1[4] = {0, 0, 0, 0};
     if constexpr (WALL == kGEN) {
       if (p.wall == kRuleIEBB) {
@@ -1064,18 +1149,18 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
       if constexpr (WALL == kGEN) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double q = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
+        const double q = (double)Storage<S>::to_float(src[k * st + p.t.at(sx, sy, sz)]);
         const FarNode n2 = far_node(p, x, y, z, k, 1);
         back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1,
                                              (double)Storage<S>::to_float(src[j * st + n2.c]));
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double a = (double)Storage<S>::to_float(src[k * st + sx + p.nx * (sy + p.ny * sz)]);
+        const double a = (double)Storage<S>::to_float(src[k * st + p.t.at(sx, sy, sz)]);
         const int tx = x + kLat.ex[k];
         const int fx = (tx + p.nx) % p.nx, fy = (y + kLat.ey[k] + p.ny) % p.ny,
                   fz = (z + kLat.ez[k] + p.nz) % p.nz;
-        double far_j = stored_to_g<S>(src[j * st + fx + p.nx * (fy + p.ny * fz)], j, p.sigma);
+        double far_j = stored_to_g<S>(src[j * st + p.t.at(fx, fy, fz)], j, p.sigma);
         const double jw = kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag;
         if (tx >= p.nx) far_j -= jw;
         if (tx < 0) far_j += jw;
@@ -1129,34 +1214,50 @@ __global__ void scatter_kernel(S* __restrict__ a, S* __restrict__ b,
   }
 }
 
-// One direction plane k, cells [c0, c0 + n), to/from a double staging buffer
-// (values are g_k; 16-bit storage is decoded / encoded with sigma).
+// Host-facing arrays are in row-major cell order (index c = x + nx (y + ny z)
+// within a z period of nz_cell planes; batches stack such periods); the
+// device buffers are in tiled order.  addr_of maps one to the other.
+__device__ __forceinline__ int addr_of(const Tiling& t, long long c, long long cell_cells,
+                                       int cell_addrs) {
+  const long long b = c / cell_cells;
+  return (int)(b * cell_addrs) + t.from_linear(c - b * cell_cells);
+}
+
+// One direction plane k, cells [c0, c0 + n) in row-major order, to/from a
+// double staging buffer (values are g_k; 16-bit storage is decoded / encoded
+// with sigma).
 template <typename S>
 __global__ void get_plane_kernel(const S* __restrict__ plane, const uint32_t* __restrict__ flags,
-                                 int k, double sigma, int c0, int n, double* __restrict__ out) {
+                                 Tiling t, long long cell_cells, int cell_addrs, int k,
+                                 double sigma, int c0, int n, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = (flags[c0 + i] & kSolid) ? 0.0 : stored_to_g<S>(plane[c0 + i], k, sigma);
+  const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
+  out[i] = (flags[a] & kSolid) ? 0.0 : stored_to_g<S>(plane[a], k, sigma);
 }
 
 template <typename S>
-__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags, int k,
+__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags,
+                                 Tiling t, long long cell_cells, int cell_addrs, int k,
                                  double sigma, int c0, int n, const double* __restrict__ in) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (!(flags[c0 + i] & kSolid)) plane[c0 + i] = g_to_stored<S>(in[i], k, sigma);
+  const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
+  if (!(flags[a] & kSolid)) plane[a] = g_to_stored<S>(in[i], k, sigma);
 }
 
-// g = g^eq(drho, u) for fluid cells [c0, c0 + n); stage = drho | ux | uy | uz
-// blocks of n doubles (all-zero staging gives the rest state).
+// g = g^eq(drho, u) for fluid cells [c0, c0 + n) (row-major order); stage =
+// drho | ux | uy | uz blocks of n doubles (all-zero staging gives the rest
+// state).
 template <typename S>
 __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
+                               Tiling t, long long cell_cells, int cell_addrs,
                                long long stride, double sigma, int c0, int n,
                                const double* __restrict__ stage) {
   using C = typename ComputeOf<S>::type;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int c = c0 + i;
+  const int c = addr_of(t, c0 + i, cell_cells, cell_addrs);
   if (flags[c] & kSolid) return;
   const C rho = (C)stage[i], ux = (C)stage[n + i], uy = (C)stage[2 * n + i],
           uz = (C)stage[3 * n + i];
@@ -1171,14 +1272,15 @@ __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__
   for (int k = 0; k < kQ; ++k) buf[k * stride + c] = g_to_stored<S>((double)g[k], k, sigma);
 }
 
-// drho, u of cells [c0, c0 + n) into stage (drho | ux | uy | uz blocks).
+// drho, u of cells [c0, c0 + n) (row-major order) into stage (drho | ux |
+// uy | uz blocks).
 template <typename S>
 __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                             long long stride, double sigma, int c0, int n,
-                             double* __restrict__ stage) {
+                             Tiling t, long long cell_cells, int cell_addrs, long long stride,
+                             double sigma, int c0, int n, double* __restrict__ stage) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int c = c0 + i;
+  const int c = addr_of(t, c0 + i, cell_cells, cell_addrs);
   double rho = 0, ux = 0, uy = 0, uz = 0;
   if (!(flags[c] & kSolid)) {
     double g[kQ];
@@ -1196,8 +1298,8 @@ __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restri
 // a value leaves the normal range); used to move the 16-bit storage scale.
 template <typename S>
 __global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                               long long stride, int ncell, float factor) {
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+                               long long stride, int naddr, float factor) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < naddr;
        c += (long long)gridDim.x * blockDim.x) {
     if (flags[c] & kSolid) continue;
 #pragma unroll

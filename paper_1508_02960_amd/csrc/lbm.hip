@@ -28,6 +28,10 @@ struct lbm_domain_s {
   // derived
   long long stride = 0;  // elements per direction plane
   size_t elem = 0;       // bytes per stored population
+  Tiling tiling{};       // tiled cell order of the device buffers
+  long long naddr = 0;   // device cell addresses (cells plus tile padding)
+  long long cell_addrs = 0;  // addresses per z period (one batch cell, or the box)
+  int waves = 16;        // wavefronts (tiles) per step workgroup
   bool streaming = false;  // non-temporal stores in the step kernels
   double nu = 0, omega_p = 0, omega_m = 0, s_e = 0, s_zeta = 0;
   double sigma = 1.0;    // 16-bit storage scale (h = sigma g / w), a power of two
@@ -41,6 +45,7 @@ struct lbm_domain_s {
   void* buf[2] = {nullptr, nullptr};
   int cur = 0;  // buf[cur] holds the current state
   uint32_t* flags = nullptr;
+  uint8_t* cls = nullptr;  // class byte per cell (kClsSolid, kClsLinks)
   long long* link_slot = nullptr;
   double* link_coef = nullptr;
   double* partials = nullptr;   // per-block partial sums
@@ -56,7 +61,7 @@ struct lbm_domain_s {
   int batch = 0;
   long long cell_size = 0;            // cells per batch cell
   std::vector<lbm_cell_params> cellp;  // per-cell tau, Lambda, delta_rho
-  int bby = 0, zper = 1;              // batch launch shape: rows per block, z planes per block
+  int bby = 0, zper = 1;              // batch launch shape: wavefronts (tiles) per block, z planes per block
   int solid_writes = 0;               // which solid cells store (StepParams::solid_writes)
   StepParams* d_cells = nullptr;
   int* d_active = nullptr;      // cells stepped in a residual run
@@ -66,7 +71,7 @@ struct lbm_domain_s {
   int* d_nactive = nullptr;
   std::vector<CellStatus> status_host;
   // layout offsets
-  size_t off_buf[2] = {0, 0}, off_flags = 0, off_slot = 0, off_coef = 0, off_part = 0,
+  size_t off_buf[2] = {0, 0}, off_flags = 0, off_cls = 0, off_slot = 0, off_coef = 0, off_part = 0,
          off_part2 = 0, off_res = 0, off_stage = 0, off_cells = 0, off_active = 0,
          off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, total = 0;
 };
@@ -123,15 +128,26 @@ double pick_sigma(double m) {
 // HBM channel: round the cell count up to 1024 elements, plus 512 elements.
 long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
 
-// Workgroups cover full x rows (up to 512 cells) and 256/bx rows in y.
-dim3 step_block(int nx) {
-  const int bx = std::min(512, ((nx + 63) / 64) * 64);
-  const int by = std::max(1, 256 / bx);
-  return dim3(bx, by, 1);
+// Tiles of 64 cells: 8 x 8 for 4- and 8-byte storage, 16 x 4 for 2-byte
+// storage (measured on the 512^3 sphere pack: these shapes fetch the fewest
+// partly used lines and step fastest for their element size).
+Tiling make_tiling(int nx, int ny, size_t elem) {
+  Tiling t{};
+  t.nx = nx;
+  t.ny = ny;
+  t.tw_log2 = elem == 2 ? 4 : 3;
+  t.th_log2 = 6 - t.tw_log2;
+  t.ntx = (nx + (1 << t.tw_log2) - 1) >> t.tw_log2;
+  t.nty = (ny + (1 << t.th_log2) - 1) >> t.th_log2;
+  t.plane = t.ntx * t.nty * 64;
+  return t;
 }
-dim3 step_grid(int nx, int ny, int nz) {
-  const dim3 b = step_block(nx);
-  return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y, nz);
+
+// Step workgroups: `waves` wavefronts take consecutive tiles of one z plane.
+dim3 step_block(lbm_domain d) { return dim3(64, d->waves, 1); }
+dim3 step_grid(lbm_domain d) {
+  const int tiles = d->tiling.ntx * d->tiling.nty;
+  return dim3((tiles + d->waves - 1) / d->waves, 1, d->geo.nz);
 }
 
 // Non-temporal stores pay once the two state buffers are well beyond the
@@ -140,11 +156,19 @@ dim3 step_grid(int nx, int ny, int nz) {
 constexpr size_t kStreamingBytes = size_t(1) << 30;
 
 void layout(lbm_domain d) {
-  const int64_t n = d->geo.ncell;
-  d->stride = plane_stride(n);
   d->elem = storage_bytes(d->p.storage);
-  d->streaming = (d->p.storage == LBM_FP32 || d->p.storage == LBM_FP64) &&
-                 2 * (size_t)kQ * (size_t)d->stride * d->elem > kStreamingBytes;
+  d->tiling = make_tiling(d->geo.nx, d->geo.ny, d->elem);
+  d->cell_addrs = (long long)d->tiling.plane * d->geo.nz_cell;
+  d->naddr = (long long)d->tiling.plane * d->geo.nz;
+  const int64_t n = d->naddr;
+  d->stride = plane_stride(n);
+  // 16 wavefronts (128 x 8 cells for 8 x 8 tiles) for 4- and 8-byte storage,
+  // 8 (128 x 4 cells) for 2-byte storage; never more than a plane has tiles
+  const int tiles = d->tiling.ntx * d->tiling.nty;
+  d->waves = d->elem == 2 ? 8 : 16;
+  while (d->waves > 1 && d->waves / 2 >= tiles) d->waves /= 2;
+  static_assert(16 * 64 <= kStepThreads, "step workgroups exceed the kernel's launch bound");
+  d->streaming = 2 * (size_t)kQ * (size_t)d->stride * d->elem > kStreamingBytes;
   size_t o = 0;
   const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
   d->off_buf[0] = o;
@@ -153,18 +177,19 @@ void layout(lbm_domain d) {
   o += bufb;
   d->off_flags = o;
   o += align256((size_t)n * 4);
+  d->off_cls = o;
+  o += align256((size_t)n);
   const size_t nl = d->geo.link_cell.size();
   d->off_slot = o;
   o += align256(std::max<size_t>(nl, 1) * 8);
   d->off_coef = o;
   o += align256(std::max<size_t>(nl, 1) * 8);
-  const dim3 sg = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
+  const dim3 sg = step_grid(d);
   d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
   if (d->batch) {
-    // most blocks: one row and one z plane per block
-    const long long bx = std::min(512, ((d->geo.nx + 63) / 64) * 64);
+    // most blocks: one tile and one z plane per block
     d->n_partials = std::max<long long>(
-        d->n_partials, ((d->geo.nx + bx - 1) / bx) * (long long)d->geo.ny * d->geo.nz);
+        d->n_partials, (long long)d->tiling.ntx * d->tiling.nty * d->geo.nz);
   }
   d->off_part = o;
   o += align256((size_t)d->n_partials * kRedVals * 8);
@@ -193,8 +218,12 @@ void layout(lbm_domain d) {
   d->total = o;
 }
 
+// Cells of one z period in row-major host order (one batch cell, or the box).
+long long cell_cells(lbm_domain d) { return (long long)d->geo.nx * d->geo.ny * d->geo.nz_cell; }
+
 StepParams step_params(lbm_domain d) {
   StepParams sp;
+  sp.t = d->tiling;
   sp.nx = d->geo.nx;
   sp.ny = d->geo.ny;
   sp.nz = d->geo.nz;
@@ -242,9 +271,7 @@ const void* step_fn(int collision, int wall) {
 
 template <typename S, bool RED>
 const void* step_fn_store(bool streaming, int collision, int wall) {
-  if constexpr (std::is_same_v<S, float> || std::is_same_v<S, double>) {
-    if (streaming) return step_fn<S, RED, true>(collision, wall);
-  }
+  if (streaming) return step_fn<S, RED, true>(collision, wall);
   return step_fn<S, RED, false>(collision, wall);
 }
 
@@ -273,10 +300,11 @@ lbm_status launch_step(lbm_domain d, bool red) {
   StepParams sp = step_params(d);
   const void* src = d->buf[d->cur];
   void* dst = d->buf[1 - d->cur];
+  const uint8_t* cl = d->cls;
   uint32_t* fl = d->flags;
   double* part = d->partials;
-  void* args[] = {(void*)&src, (void*)&dst, (void*)&fl, (void*)&sp, (void*)&part};
-  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz), block = step_block(d->geo.nx);
+  void* args[] = {(void*)&src, (void*)&dst, (void*)&cl, (void*)&fl, (void*)&sp, (void*)&part};
+  const dim3 grid = step_grid(d), block = step_block(d);
   HIP_OK(d, hipLaunchKernel(step_function(d, red), grid, block, args, 0, d->stream));
   d->cur = 1 - d->cur;
   ++d->step_count;
@@ -289,15 +317,16 @@ lbm_status build_graph(lbm_domain d, int from) {
   hipGraph_t g = nullptr;
   HIP_OK(d, hipGraphCreate(&g, 0));
   StepParams sp = step_params(d);
+  const uint8_t* cl = d->cls;
   uint32_t* fl = d->flags;
   double* part = d->partials;
-  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz), block = step_block(d->geo.nx);
+  const dim3 grid = step_grid(d), block = step_block(d);
   const void* fn = step_function(d, false);
   hipGraphNode_t prev = nullptr;
   for (int i = 0; i < kGraphSteps; ++i) {
     const void* src = d->buf[(from + i) & 1];
     void* dst = d->buf[(from + i + 1) & 1];
-    void* args[] = {(void*)&src, (void*)&dst, (void*)&fl, (void*)&sp, (void*)&part};
+    void* args[] = {(void*)&src, (void*)&dst, (void*)&cl, (void*)&fl, (void*)&sp, (void*)&part};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
     kp.gridDim = grid;
@@ -344,13 +373,10 @@ lbm_status enqueue_steps(lbm_domain d, int64_t n) {
 
 // ---- batches
 
-dim3 batch_block(lbm_domain d) {
-  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
-  return dim3(bx, d->bby, 1);
-}
+dim3 batch_block(lbm_domain d) { return dim3(64, d->bby, 1); }
 dim3 batch_grid(lbm_domain d) {
-  const dim3 b = batch_block(d);
-  return dim3((d->geo.nx + b.x - 1) / b.x, (d->geo.ny + b.y - 1) / b.y,
+  const int tiles = d->tiling.ntx * d->tiling.nty;
+  return dim3((tiles + d->bby - 1) / d->bby, 1,
               (unsigned)((long long)d->batch * d->geo.nz_cell / d->zper));
 }
 
@@ -390,6 +416,7 @@ const void* batch_function(lbm_domain d, bool red) {
 struct BatchArgs {
   const void* src;
   void* dst;
+  const uint8_t* cls;
   const uint32_t* flags;
   const StepParams* cells;
   const int* active;
@@ -397,26 +424,28 @@ struct BatchArgs {
   long long cell_size;
   int zper;
   double* partials;
-  void* ptrs[9];
+  void* ptrs[10];
   void fill(lbm_domain d, int from, const int* act) {
     src = d->buf[from];
     dst = d->buf[1 - from];
+    cls = d->cls;
     flags = d->flags;
     cells = d->d_cells;
     active = act;
     nz_cell = d->geo.nz_cell;
-    cell_size = d->cell_size;
+    cell_size = d->cell_addrs;
     zper = d->zper;
     partials = d->partials;
     ptrs[0] = &src;
     ptrs[1] = &dst;
-    ptrs[2] = &flags;
-    ptrs[3] = &cells;
-    ptrs[4] = &active;
-    ptrs[5] = &nz_cell;
-    ptrs[6] = &cell_size;
-    ptrs[7] = &zper;
-    ptrs[8] = &partials;
+    ptrs[2] = &cls;
+    ptrs[3] = &flags;
+    ptrs[4] = &cells;
+    ptrs[5] = &active;
+    ptrs[6] = &nz_cell;
+    ptrs[7] = &cell_size;
+    ptrs[8] = &zper;
+    ptrs[9] = &partials;
   }
 };
 
@@ -462,7 +491,7 @@ lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, dou
   };
   const dim3 grid = batch_grid(d), block = batch_block(d);
   const long long blocks_per_cell =
-      (long long)grid.x * grid.y * ((long long)d->geo.nz_cell / d->zper);
+      (long long)grid.x * grid.y * ((long long)d->geo.nz_cell / d->zper);  // grid.y is 1
   int parity = from;
   hipError_t e = hipSuccess;
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
@@ -529,6 +558,7 @@ lbm_status upload_cell_params(lbm_domain d) {
   for (int b = 0; b < d->batch; ++b) {
     const lbm_cell_params& c = d->cellp[b];
     StepParams& sp = t[b];
+    sp.t = d->tiling;
     sp.nx = d->geo.nx;
     sp.ny = d->geo.ny;
     sp.nz = d->geo.nz_cell;
@@ -587,11 +617,11 @@ lbm_status batch_run(lbm_domain d, double tol, int64_t max_steps, int64_t* steps
   if (d->p.storage == LBM_FP64)
     batch_align_kernel<double><<<2048, 256, 0, d->stream>>>(
         (double*)d->buf[d->cur], (const double*)d->buf[1 - d->cur], d->d_status, d->cur,
-        d->cell_size, d->stride, d->batch);
+        d->cell_addrs, d->stride, d->batch);
   else
     batch_align_kernel<float><<<2048, 256, 0, d->stream>>>(
         (float*)d->buf[d->cur], (const float*)d->buf[1 - d->cur], d->d_status, d->cur,
-        d->cell_size, d->stride, d->batch);
+        d->cell_addrs, d->stride, d->batch);
   HIP_OK(d, hipGetLastError());
   d->status_host.resize(d->batch);
   HIP_OK(d, hipMemcpyAsync(d->status_host.data(), d->d_status, d->batch * sizeof(CellStatus),
@@ -628,7 +658,7 @@ lbm_status fetch_result(lbm_domain d, double* vals) {
 lbm_status step_and_reduce(lbm_domain d, double* vals) {
   lbm_status st = launch_step(d, true);
   if (st != LBM_OK) return st;
-  const dim3 grid = step_grid(d->geo.nx, d->geo.ny, d->geo.nz);
+  const dim3 grid = step_grid(d);
   const long long nb = (long long)grid.x * grid.y * grid.z;
   const int mask = (1 << 4) | (1 << 6);
   reduce_partials_kernel<<<kRedThreads, kRedThreads, 0, d->stream>>>(d->partials, nb, mask,
@@ -640,11 +670,11 @@ lbm_status step_and_reduce(lbm_domain d, double* vals) {
 
 // Reduce the stored current state; vals as above without slot 6.
 lbm_status reduce_state(lbm_domain d, double* vals) {
-  const int ncell = (int)d->geo.ncell;
+  const int naddr = (int)d->naddr;
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     reduce_state_kernel<S><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-        (const S*)d->buf[d->cur], d->flags, d->stride, ncell, d->sigma, d->partials);
+        (const S*)d->buf[d->cur], d->flags, d->stride, naddr, d->sigma, d->partials);
     return 0;
   });
   reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 1 << 4,
@@ -665,7 +695,7 @@ lbm_status adjust_scale(lbm_domain d, double m) {
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     rescale_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[d->cur], d->flags, d->stride,
-                                                   (int)d->geo.ncell, factor);
+                                                   (int)d->naddr, factor);
     return 0;
   });
   HIP_OK(d, hipGetLastError());
@@ -716,7 +746,10 @@ LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere
   const lbm_params& p = *params;
   if (p.nx < 1 || p.ny < 1 || p.nz < 1) return bad("box edges must be >= 1");
   const int64_t ncell = (int64_t)p.nx * p.ny * p.nz;
-  if (ncell >= (int64_t(1) << 31)) return bad("nx*ny*nz must be below 2^31");
+  // the device addresses include the padding of x and y to whole tiles
+  const int64_t padded = (int64_t)((p.nx + 15) / 16 * 16) * ((p.ny + 7) / 8 * 8) * p.nz;
+  if (ncell >= (int64_t(1) << 31) || padded >= (int64_t(1) << 31))
+    return bad("nx*ny*nz (padded to whole tiles) must be below 2^31");
   if (p.ny > 65535 || p.nz > 65535) return bad("ny and nz must be at most 65535");
   if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return bad("tau must be finite and > 1/2");
   if (p.collision < LBM_SRT || p.collision > LBM_MRT) return bad("unknown collision");
@@ -824,6 +857,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->buf[1] = d->ws + d->off_buf[1];
   d->cur = 0;
   d->flags = (uint32_t*)(d->ws + d->off_flags);
+  d->cls = (uint8_t*)(d->ws + d->off_cls);
   d->link_slot = (long long*)(d->ws + d->off_slot);
   d->link_coef = (double*)(d->ws + d->off_coef);
   d->partials = (double*)(d->ws + d->off_part);
@@ -844,9 +878,24 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
                                                                       d->batch, 0);
   }
 
-  const int64_t n = d->geo.ncell;
-  HIP_OK(d, hipMemcpyAsync(d->flags, d->geo.flags.data(), n * 4, hipMemcpyHostToDevice,
-                           d->stream));
+  // flag words and class bytes in tiled order (padding: solid)
+  {
+    const int64_t na = d->naddr;
+    std::vector<uint32_t> fl((size_t)na, kSolid);
+    std::vector<uint8_t> cl((size_t)na, kClsSolid);
+    const int64_t cc = (int64_t)d->geo.nx * d->geo.ny * d->geo.nz_cell;
+    for (int64_t c = 0; c < d->geo.ncell; ++c) {
+      const int64_t b = c / cc;
+      const int64_t a = b * d->cell_addrs + d->tiling.from_linear(c - b * cc);
+      const uint32_t w = d->geo.flags[(size_t)c];
+      fl[(size_t)a] = w;
+      cl[(size_t)a] = (uint8_t)(((w & kSolid) ? kClsSolid : 0) | ((w & kLinkMask) ? kClsLinks : 0));
+    }
+    HIP_OK(d, hipMemcpyAsync(d->flags, fl.data(), (size_t)na * 4, hipMemcpyHostToDevice,
+                             d->stream));
+    HIP_OK(d, hipMemcpyAsync(d->cls, cl.data(), (size_t)na, hipMemcpyHostToDevice, d->stream));
+    HIP_OK(d, hipStreamSynchronize(d->stream));  // fl and cl are local host buffers
+  }
   // Wall-link coefficients into the slot of the solid pull source of each
   // link: link (c, j) is pulled as direction k = opp(j) from c + e_j.
   const size_t nl = d->geo.link_cell.size();
@@ -860,8 +909,8 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     // z wraps within the periodic cell (the whole box for one domain)
     const int zc = d->geo.nz_cell, z0 = z - z % zc;
     const int xs = (x + kLat.ex[j] + nx) % nx, ys = (y + kLat.ey[j] + ny) % ny,
-              zs = z0 + (z - z0 + kLat.ez[j] + zc) % zc;
-    const int64_t s = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+              zs = (z - z0 + kLat.ez[j] + zc) % zc;
+    const int64_t s = (int64_t)(z0 / zc) * d->cell_addrs + d->tiling.at(xs, ys, zs);
     slot[i] = (long long)kLat.opp[j] * d->stride + s;
     const double q = d->geo.link_q[i];
     // eq. (CLI): a = (1 - 2q)/(1 + 2q); links without a second fluid node
@@ -925,7 +974,8 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const
     with_storage(d->p.storage, [&](auto tag) {
       using S = decltype(tag);
       init_eq_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-          (S*)d->buf[d->cur], d->flags, d->stride, d->sigma, (int)c0, cnt, d->stage);
+          (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, (int)c0, cnt,
+          d->stage);
       return 0;
     });
     HIP_OK(d, hipGetLastError());
@@ -955,7 +1005,7 @@ LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
       with_storage(d->p.storage, [&](auto tag) {
         using S = decltype(tag);
         set_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-            (S*)plane, d->flags, k, d->sigma, (int)c0, cnt, d->stage);
+            (S*)plane, d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
         return 0;
       });
       HIP_OK(d, hipGetLastError());
@@ -979,7 +1029,7 @@ LBM_API lbm_status lbm_get_state(lbm_domain d, double* g) {
       with_storage(d->p.storage, [&](auto tag) {
         using S = decltype(tag);
         get_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-            (const S*)plane, d->flags, k, d->sigma, (int)c0, cnt, d->stage);
+            (const S*)plane, d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
         return 0;
       });
       HIP_OK(d, hipGetLastError());
@@ -1060,7 +1110,8 @@ LBM_API lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u) {
     with_storage(d->p.storage, [&](auto tag) {
       using S = decltype(tag);
       macro_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-          (const S*)d->buf[d->cur], d->flags, d->stride, d->sigma, (int)c0, cnt, d->stage);
+          (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, (int)c0, cnt,
+          d->stage);
       return 0;
     });
     HIP_OK(d, hipGetLastError());
@@ -1087,7 +1138,7 @@ LBM_API lbm_status lbm_macroscopic_device(lbm_domain d, double* fields) {
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     macro_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
-        (const S*)d->buf[d->cur], d->flags, d->stride, d->sigma, 0, n, fields);
+        (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, 0, n, fields);
     return 0;
   });
   HIP_OK(d, hipGetLastError());
@@ -1106,7 +1157,7 @@ LBM_API lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* field
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     init_eq_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
-        (S*)d->buf[d->cur], d->flags, d->stride, d->sigma, 0, n, fields);
+        (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, 0, n, fields);
     return 0;
   });
   HIP_OK(d, hipGetLastError());
@@ -1264,7 +1315,7 @@ LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
   d->nu = (cells[0].tau - 0.5) / 3.0;
   d->omega_p = 1.0 / cells[0].tau;
   d->omega_m = d->omega_p;
-  d->bby = std::max(1, 256 / std::min(kBatchThreads, ((p.nx + 63) / 64) * 64));
+  d->bby = 4;  // wavefronts (tiles) per workgroup until set or autotuned
   d->zper = 1;
   layout(d);
   choose_sigma(d, 0.0);
@@ -1296,12 +1347,13 @@ LBM_API lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64
   return LBM_OK;
 }
 
-LBM_API lbm_status lbm_batch_set_shape(lbm_domain d, int32_t by, int32_t zper) {
+LBM_API lbm_status lbm_batch_set_shape(lbm_domain d, int32_t waves, int32_t zper) {
   if (!d || !d->batch) return LBM_ERR_INVALID_ARG;
-  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
-  if (by < 1 || bx * by > kBatchThreads || zper < 1 || d->geo.nz_cell % zper != 0)
-    return fail(d, LBM_ERR_INVALID_ARG, "by*row width must be <= 1024 and zper must divide nz");
-  d->bby = by;
+  if (waves < 1 || 64 * waves > kBatchThreads || zper < 1 || d->geo.nz_cell % zper != 0)
+    return fail(d, LBM_ERR_INVALID_ARG,
+                "waves must lie in [1, " + std::to_string(kBatchThreads / 64) +
+                    "] and zper must divide nz");
+  d->bby = waves;
   d->zper = zper;
   return LBM_OK;
 }
@@ -1324,7 +1376,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
   if (st != LBM_OK) return st;
   if (!d->batch) return fail(d, LBM_ERR_STATE, "autotune applies to batches");
   if (steps < 1) return fail(d, LBM_ERR_INVALID_ARG, "steps must be >= 1");
-  const int bx = std::min(kBatchThreads, ((d->geo.nx + 63) / 64) * 64);
+  const int tiles = d->tiling.ntx * d->tiling.nty;
   hipEvent_t e0, e1;
   HIP_OK(d, hipEventCreate(&e0));
   HIP_OK(d, hipEventCreate(&e1));
@@ -1334,7 +1386,7 @@ LBM_API lbm_status lbm_batch_autotune(lbm_domain d, int32_t steps, int32_t* by_o
     d->solid_writes = mode;
     st = upload_cell_params(d);
     if (st != LBM_OK) break;
-    for (int by = 1; by * bx <= kBatchThreads && by <= d->geo.ny; by *= 2) {
+    for (int by = 1; 64 * by <= kBatchThreads && by <= tiles; by *= 2) {
       for (int zp = 1; zp <= 8 && zp <= d->geo.nz_cell; zp *= 2) {
         if (d->geo.nz_cell % zp) continue;
         d->bby = by;

@@ -28,8 +28,10 @@ EXPORTS = (
     "lbm_drag", "lbm_set_delta_rho", "lbm_synchronize", "lbm_destroy", "lbm_status_string",
     "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
     "lbm_batch_autotune", "lbm_macroscopic_device", "lbm_init_equilibrium_device",
-    "lbm_set_solid_writes", "lbm_get_solid_writes",
+    "lbm_set_solid_writes", "lbm_get_solid_writes", "lbm_bandwidth_probe",
 )
+
+PROBES = {"read": 0, "write": 1, "copy": 2, "gather19": 3}
 
 
 class LbmError(RuntimeError):
@@ -111,6 +113,7 @@ def library():
         "lbm_batch_autotune": [vp, i32, P(i32), P(i32), P(d)],
         "lbm_set_solid_writes": [vp, i32],
         "lbm_get_solid_writes": [vp, P(i32)],
+        "lbm_bandwidth_probe": [i32, vp, vp, i64, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -122,6 +125,17 @@ def library():
     lib.lbm_last_error.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+def bandwidth_probe(kind: str, src, dst, n: int, stream) -> None:
+    """Enqueue one attainable-bandwidth probe (lbm_bandwidth_probe) on a torch
+    stream; src and dst are device tensors (dst only for "write")."""
+    st = library().lbm_bandwidth_probe(PROBES[kind],
+                                       C.c_void_p(src.data_ptr()) if src is not None else None,
+                                       C.c_void_p(dst.data_ptr()), int(n),
+                                       C.c_void_p(stream.cuda_stream))
+    if st != 0:
+        raise LbmError(st, f"bandwidth probe {kind} rejected")
 
 
 def _ptr(a):

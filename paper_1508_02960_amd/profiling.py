@@ -1,16 +1,14 @@
-"""rocprofv3 helpers: counter calibration with a plain copy and summaries.
+"""rocprofv3 helpers: kernel-time summaries and HBM traffic from byte counters.
 
-    python -m paper_1508_02960_amd.profiling calib
-        one plain device-to-device copy of 1 GiB, three times (run it under
-        rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE to get the factors
-        that turn each counter into bytes)
     python -m paper_1508_02960_amd.profiling stats <kernel_stats.csv> <out.md> <command...>
         markdown table of a --kernel-trace --stats run
-    python -m paper_1508_02960_amd.profiling traffic <fetch.csv> <write.csv>
-        <calib_fetch.csv> <calib_write.csv> <kernel> <workload> <n_fluid>
-        <bytes_per_update> <out.md> <out.json> <command...>
-        HBM bytes per launch of <kernel> from the two counter runs, scaled by
-        what the same counters read for the calibration copy.
+    python -m paper_1508_02960_amd.profiling traffic <fetch.csv> <write.csv> <probe_bytes>
+        <kernel> <workload> <n_fluid> <bytes_per_update> <out.md> <out.json> <command...>
+        HBM bytes per launch of <kernel> from a FETCH_SIZE run and a WRITE_SIZE run
+        of bench.py.  The same runs hold the bandwidth probes of known byte counts
+        (lbm_bandwidth_probe: read, write and copy of <probe_bytes> bytes); the
+        read probe scales FETCH_SIZE to bytes, the write probe scales WRITE_SIZE,
+        and the copy probe, read and written through both, checks both factors.
 """
 from __future__ import annotations
 
@@ -22,7 +20,6 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hpp")
-CALIB_BYTES = 1 << 30
 
 
 def kernel_source_hash() -> str:
@@ -30,31 +27,23 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def calib() -> None:
-    import torch
-
-    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(f"calib: 3 device-to-device copies of {CALIB_BYTES} bytes")
+def short_name(full: str) -> str:
+    """Kernel name without namespace, template arguments and signature:
+    'void lbm::step_kernel<float, 1, 1, false, true>(...)' -> 'step_kernel'."""
+    n = full.replace("(anonymous namespace)::", "")
+    n = n.split("(")[0].split("<")[0].strip()
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("::")[-1]
 
 
 def _counter_means(path: str):
-    """{kernel name: mean counter value (KiB) per dispatch} of one --pmc run."""
+    """{short kernel name: mean counter value (KiB) per dispatch} of one --pmc run."""
     acc = {}
     with open(path) as f:
         for r in csv.DictReader(f):
-            name = r["Kernel_Name"].split("(")[0].strip()
-            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+            acc.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
-
-
-def _calib_kernel(means):
-    # the dispatch of the calibration copy: the kernel with the largest counter
-    return max(means.items(), key=lambda kv: kv[1])
 
 
 def stats(path: str, out: str, command: str) -> None:
@@ -69,14 +58,15 @@ def stats(path: str, out: str, command: str) -> None:
     open(out, "w").write("\n".join(lines) + "\n")
 
 
-def traffic(fetch, write, cfetch, cwrite, kernel, workload, n_fluid, bpu, out_md, out_json,
+def traffic(fetch, write, probe_bytes, kernel, workload, n_fluid, bpu, out_md, out_json,
             command) -> None:
     fm, fc = _counter_means(fetch)
     wm, wc = _counter_means(write)
-    cf_name, cf = _calib_kernel(_counter_means(cfetch)[0])
-    cw_name, cw = _calib_kernel(_counter_means(cwrite)[0])
-    f_factor = CALIB_BYTES / (cf * 1024.0)
-    w_factor = CALIB_BYTES / (cw * 1024.0)
+    nb = float(probe_bytes)
+    f_factor = nb / (fm["read_kernel"] * 1024.0)
+    w_factor = nb / (wm["write_kernel"] * 1024.0)
+    copy_read = fm["copy_kernel"] * 1024.0 * f_factor / nb
+    copy_write = wm["copy_kernel"] * 1024.0 * w_factor / nb
     kf = fm[kernel] * 1024.0 * f_factor
     kw = wm[kernel] * 1024.0 * w_factor
     alg = int(n_fluid) * int(bpu)
@@ -87,15 +77,19 @@ def traffic(fetch, write, cfetch, cwrite, kernel, workload, n_fluid, bpu, out_md
         "hbm_bytes_per_launch": kf + kw,
         "algorithmic_bytes_per_launch": alg,
         "fetch_factor": f_factor, "write_factor": w_factor,
-        "calibration_kernel": cf_name, "dispatches": fc[kernel],
+        "copy_probe_read_over_bytes": copy_read, "copy_probe_write_over_bytes": copy_write,
+        "probe_bytes": int(nb), "dispatches": fc[kernel],
         "command": command,
     }
     json.dump(rec, open(out_json, "w"), indent=1)
     lines = [f"# HBM traffic of `{kernel}` ({workload})", "",
-             f"Command: `{command}`", "",
-             "Counters are KiB per dispatch.  Each is scaled by what the same counter reads for "
-             f"a plain copy of {CALIB_BYTES} bytes (`{cf_name}`): FETCH_SIZE x{f_factor:.3f}, "
-             f"WRITE_SIZE x{w_factor:.3f}.", "",
+             f"Command (run twice, with `--pmc FETCH_SIZE` and with `--pmc WRITE_SIZE`): "
+             f"`{command}`", "",
+             "Counters are KiB per dispatch.  They are scaled by what the same counters read for "
+             f"the bandwidth probes of {int(nb)} bytes in the same runs: FETCH_SIZE x{f_factor:.3f} "
+             f"(read probe), WRITE_SIZE x{w_factor:.3f} (write probe).  Check on the copy probe "
+             f"(reads and writes {int(nb)} bytes): scaled reads {copy_read:.3f}x, scaled writes "
+             f"{copy_write:.3f}x the bytes it moves.", "",
              "| quantity | per launch |", "|---|---|",
              f"| FETCH_SIZE (raw KiB) | {fm[kernel]:.1f} |",
              f"| WRITE_SIZE (raw KiB) | {wm[kernel]:.1f} |",
@@ -103,7 +97,10 @@ def traffic(fetch, write, cfetch, cwrite, kernel, workload, n_fluid, bpu, out_md
              f"| written bytes (scaled) | {kw / 1e6:.2f} MB |",
              f"| total HBM traffic | {(kf + kw) / 1e6:.2f} MB |",
              f"| algorithmic bytes ({n_fluid} fluid cells x {bpu} B) | {alg / 1e6:.2f} MB |",
+             f"| reads / algorithmic reads | {kf / (alg / 2):.3f} |",
+             f"| writes / algorithmic writes | {kw / (alg / 2):.3f} |",
              f"| traffic / algorithmic | {(kf + kw) / alg:.3f} |",
+             f"| dispatches averaged | {fc[kernel]} |",
              f"| kernel source sha256[:16] | {kernel_source_hash()} |"]
     open(out_md, "w").write("\n".join(lines) + "\n")
 
@@ -113,12 +110,10 @@ def main(argv) -> int:
         print(__doc__)
         return 2
     cmd = argv[0]
-    if cmd == "calib":
-        calib()
-    elif cmd == "stats":
+    if cmd == "stats":
         stats(argv[1], argv[2], " ".join(argv[3:]))
     elif cmd == "traffic":
-        traffic(*argv[1:11], " ".join(argv[11:]))
+        traffic(*argv[1:10], " ".join(argv[10:]))
     else:
         print(__doc__)
         return 2

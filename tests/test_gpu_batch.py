@@ -84,6 +84,35 @@ def test_batch_run_to_residual_per_cell(orc):
     b.close()
 
 
+def test_batch_residual_with_largest_workgroups(orc):
+    """Regression test of the per-block FP64 reduction at the largest batch
+    workgroup (16 wavefronts, 1024 threads, every wavefront holding fluid
+    cells): per-cell stopping steps equal the oracle's and K_D agrees to
+    1e-10 (FP64), as with the default shape."""
+    shape = (4, 32, 32)  # 16 tiles of 8 x 8 per plane: one plane per workgroup
+    rng = np.random.default_rng(11)
+    cells = []
+    for i in range(3):
+        sp = inputs.random_spheres(shape, 3, (3.0, 5.0), seed=110 + i)
+        sp[:, 3] = np.minimum(sp[:, 3], 3.9)  # radii below the smallest edge
+        cells.append(dict(spheres=sp, tau=float(rng.uniform(1.0, 1.3)), magic=3 / 16,
+                          delta_rho=float(rng.uniform(0.5, 1.5) * 1e-6)))
+    b = lbm.Batch(shape, cells, wall="cli", storage="fp64", check_interval=50)
+    b.set_shape(16, 2)
+    st, _, _ = b.run_to_residual(1e-7, 60000)
+    assert st == "converged"
+    r = b.results()
+    for i, c in enumerate(cells):
+        o = orc.Oracle(shape, tau=c["tau"], magic=c["magic"], delta_rho=c["delta_rho"],
+                       collision="trt", wall="cli", spheres=c["spheres"])
+        o.init()
+        so, no, _ = o.run_to_residual(1e-7, 60000, interval=50)
+        assert so == "converged" and r["status"][i] == "converged"
+        assert r["steps"][i] == no, (i, r["steps"][i], no)
+        assert abs(r["K_D"][i] / o.permeability() - 1) < 1e-10
+    b.close()
+
+
 def test_batch_shapes_give_identical_bits():
     """The launch shape and solid-write mode chosen by the autotuner change
     scheduling only."""

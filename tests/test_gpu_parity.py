@@ -78,6 +78,71 @@ def test_fp32_velocity_parity(orc, collision, wall):
     d.close()
 
 
+@pytest.mark.parametrize("collision,wall", [("trt", "sbb"), ("trt", "cli"), ("mrt", "cli"),
+                                            ("mrt", "mr")])
+def test_turbulent_regime_parity(orc, collision, wall):
+    """The parameters of the 512^3 workload at Re_p ~ 5.8e3: tau = 0.5005
+    (nu = 1.7e-4), TRT with Lambda = 6e-6 (Table 1, highest Re_p range) and
+    MRT (Pan's s_zeta ~ 2.7e-3), on a small random sphere pack from a
+    perturbed equilibrium under a pressure drop, 60 steps: FP64 state within
+    1e-12 and FP32 velocity within 1e-5 of the oracle.  At this viscosity
+    both rates sit near 2, so non-equilibrium parts are barely damped."""
+    shape = (20, 22, 36)
+    sp = inputs.random_spheres(shape, 5, (2.5, 5.0), seed=91)
+    kw = dict(tau=0.5005, magic=6e-6, delta_rho=1e-4, collision=collision, wall=wall,
+              spheres=sp)
+    u0 = inputs.random_velocity(shape, 4e-3, seed=92)
+    o = orc.Oracle(shape, **kw)
+    o.init(u0=u0)
+    o.step(60)
+    fluid = o.mask == 0
+    _, uo = o.macroscopic()
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        d = lbm.Domain(shape, storage=storage, **kw)
+        d.init_equilibrium(u0=u0)
+        d.step(60)
+        if storage == "fp64":
+            assert rel(d.get_state(), o.g, fluid) < tol
+        _, ud = d.macroscopic()
+        assert rel(ud, uo, fluid) < tol, storage
+        d.close()
+
+
+def test_low_viscosity_blow_up_step_matches_oracle(orc):
+    """The turbulent workload scaled down to a 32^3 cell (sphere D = 30,
+    tau = 0.5005, pressure drop of the Re_p = 5812 target, 1% seeded random
+    start velocity) is under-resolved and blows up.  TRT (Lambda = 6e-6) and
+    MRT become unstable (non-finite or |u| > c_s) at the same check step on
+    the GPU (FP64) as in the oracle, so the blow-up belongs to the scheme at
+    this resolution, not to the kernels."""
+    import os
+
+    edge = 32
+    shape = (edge,) * 3
+    D = 240.0 * edge / 256
+    nu = (0.5005 - 0.5) / 3
+    U = 5812 * nu / D
+    K = 292.4 * (edge / 256) ** 2  # Stokes permeability of the 256^3 cell, scaled
+    drho = 3 * edge * 0.026 * U * U / np.sqrt(K)
+    u0 = 0.01 * U * inputs.random_velocity(shape, 1.0, seed=3)
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        for coll in ("mrt", "trt"):
+            kw = dict(tau=0.5005, magic=6e-6, delta_rho=drho, collision=coll, wall="cli",
+                      spheres=inputs.centred_sphere(shape, D))
+            o = orc.Oracle(shape, **kw)
+            o.init(u0=u0)
+            so, no, _ = o.run_to_residual(0.0, 6000, interval=100)
+            d = lbm.Domain(shape, storage="fp64", check_interval=100, **kw)
+            d.init_equilibrium(u0=u0)
+            sd, nd, _ = d.run_to_residual(0.0, 6000)
+            d.close()
+            assert so == sd == "unstable", (coll, so, sd)
+            assert nd == no, (coll, nd, no)
+    finally:
+        orc.set_threads(1)
+
+
 def test_config1_fp64_full_run(orc):
     """32^3 cell, centred sphere D = 24, TRT Lambda = 3/16, SBB, FP64,
     delta_rho = 2.15e-6 (Re_p ~ 1e-3), rest start, 2000 steps."""
