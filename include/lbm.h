@@ -215,6 +215,22 @@ lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* fields);
 lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
                              double* total_drho);
 
+/* lbm_mean_velocity for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same kernels and the same results bit for bit, but the
+ * reduction's scratch (1024 block partial vectors and the final vector,
+ * 65 KB) is a static device array of the library, one per GPU, held until
+ * the process ends, instead of a region of the domain's workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * the first call on a GPU looks up the array's device address.  The scratch
+ * need does not depend on the domain size (the reduction runs a fixed grid),
+ * so no size is rejected.  Every call on one GPU shares its array: calls that
+ * overlap on one GPU (from several threads or streams) race and must be
+ * serialised by the caller.  Errors as lbm_mean_velocity, plus
+ * LBM_ERR_DEVICE if the array cannot be located. */
+lbm_status lbm_mean_velocity_static(lbm_domain d, double U[3], double* max_speed,
+                                    double* total_drho);
+
 /* Darcy permeability, eq. (Darcy): K_D = nu U_x nx / dp with dp = delta_rho/3
  * (mu = nu for rho0 = 1, pressure gradient dp/nx); U_x is the superficial
  * velocity (lbm_mean_velocity).  Re_p_per_D = U_x / nu is the pore Reynolds

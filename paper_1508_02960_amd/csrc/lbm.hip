@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -39,6 +40,7 @@ struct lbm_domain_s {
   // device (inside the caller's workspace)
   bool bound = false;
   bool unstable = false;
+  int device = 0;  // GPU holding the workspace
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -668,18 +670,26 @@ lbm_status step_and_reduce(lbm_domain d, double* vals) {
   return fetch_result(d, vals);
 }
 
-// Reduce the stored current state; vals as above without slot 6.
-lbm_status reduce_state(lbm_domain d, double* vals) {
+// Reduce the stored current state; vals as above without slot 6.  The
+// kRedBlocks partial vectors go to `partials` and the final vector to
+// `result` (device buffers of kRedBlocks * kRedVals and kRedVals doubles).
+lbm_status reduce_state_into(lbm_domain d, double* partials, double* result, double* vals) {
   const int naddr = (int)d->naddr;
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     reduce_state_kernel<S><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-        (const S*)d->buf[d->cur], d->flags, d->stride, naddr, d->sigma, d->partials);
+        (const S*)d->buf[d->cur], d->flags, d->stride, naddr, d->sigma, partials);
     return 0;
   });
-  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(d->partials, kRedBlocks, 1 << 4,
-                                                       d->result);
-  return fetch_result(d, vals);
+  reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(partials, kRedBlocks, 1 << 4, result);
+  HIP_OK(d, hipGetLastError());
+  HIP_OK(d, hipMemcpyAsync(vals, result, kRedVals * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_OK(d, hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+lbm_status reduce_state(lbm_domain d, double* vals) {
+  return reduce_state_into(d, d->partials, d->result, vals);
 }
 
 // Move the 16-bit storage scale so that the largest stored magnitude
@@ -850,6 +860,11 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
                 "workspace too small: need " + std::to_string(d->total) + " bytes");
   d->bound = false;
   drop_graphs(d);
+  {
+    hipPointerAttribute_t attr{};
+    HIP_OK(d, hipPointerGetAttributes(&attr, workspace));
+    d->device = attr.device;
+  }
   d->ws = (char*)workspace;
   d->ws_bytes = bytes;
   d->stream = (hipStream_t)stream;
@@ -1165,14 +1180,9 @@ LBM_API lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* field
   return LBM_OK;
 }
 
-LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
-                                     double* total_drho) {
-  lbm_status st = check_ready(d);
-  if (st != LBM_OK) return st;
-  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
-  double v[kRedVals];
-  st = reduce_state(d, v);
-  if (st != LBM_OK) return st;
+// Outputs of lbm_mean_velocity from the reduced vector.
+static void mean_velocity_outputs(lbm_domain d, const double* v, double U[3], double* max_speed,
+                           double* total_drho) {
   const double n = (double)d->geo.ncell;
   if (U) {
     U[0] = v[0] / n;
@@ -1181,6 +1191,75 @@ LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_spee
   }
   if (max_speed) *max_speed = v[5] > 0 ? NAN : std::sqrt(v[4]);
   if (total_drho) *total_drho = v[3];
+}
+
+LBM_API lbm_status lbm_mean_velocity(lbm_domain d, double U[3], double* max_speed,
+                                     double* total_drho) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
+  double v[kRedVals];
+  st = reduce_state(d, v);
+  if (st != LBM_OK) return st;
+  mean_velocity_outputs(d, v, U, max_speed, total_drho);
+  return LBM_OK;
+}
+
+// ------------------------------------------------- no-allocation variant
+// Scratch of lbm_mean_velocity_static: the block partial sums and the final
+// vector of the state reduction live in this device array of the library
+// (one copy per GPU, held until the process ends) instead of the domain's
+// workspace.  Host code never passes the array's name to a kernel or a copy:
+// it uses the device address that hipGetSymbolAddress returns for the GPU in
+// question (kept per device below).
+constexpr int kStaticPartials = kRedBlocks;  // the state reduction's fixed grid
+constexpr int kStaticScratchDoubles = kStaticPartials * kRedVals + kRedVals;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the domain's GPU, looked up once per device
+// with that device current (the caller's current device is restored).
+lbm_status static_scratch(lbm_domain d, double** out) {
+  if (d->device < 0 || d->device >= kMaxDevices)
+    return fail(d, LBM_ERR_DEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[d->device]) {
+    int prev = 0;
+    HIP_OK(d, hipGetDevice(&prev));
+    if (prev != d->device) HIP_OK(d, hipSetDevice(d->device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != d->device) HIP_OK(d, hipSetDevice(prev));
+    if (e != hipSuccess || !p)
+      return fail(d, LBM_ERR_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[d->device] = (double*)p;
+  }
+  *out = g_scratch_ptr[d->device];
+  return LBM_OK;
+}
+}  // namespace
+
+LBM_API lbm_status lbm_mean_velocity_static(lbm_domain d, double U[3], double* max_speed,
+                                            double* total_drho) {
+  lbm_status st = check_ready(d);
+  if (st != LBM_OK) return st;
+  if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
+  // the reduction runs a fixed grid of kRedBlocks blocks whatever the domain
+  // size, so its scratch never exceeds the array; checked all the same
+  if ((long long)kRedBlocks * kRedVals + kRedVals > kStaticScratchDoubles)
+    return fail(d, LBM_ERR_INVALID_ARG, "reduction needs more scratch than the static array holds");
+  double* scr = nullptr;
+  st = static_scratch(d, &scr);
+  if (st != LBM_OK) return st;
+  double v[kRedVals];
+  st = reduce_state_into(d, scr, scr + kStaticPartials * kRedVals, v);
+  if (st != LBM_OK) return st;
+  mean_velocity_outputs(d, v, U, max_speed, total_drho);
   return LBM_OK;
 }
 

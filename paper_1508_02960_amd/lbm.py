@@ -29,6 +29,7 @@ EXPORTS = (
     "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
     "lbm_batch_autotune", "lbm_macroscopic_device", "lbm_init_equilibrium_device",
     "lbm_set_solid_writes", "lbm_get_solid_writes", "lbm_bandwidth_probe",
+    "lbm_mean_velocity_static",
 )
 
 PROBES = {"read": 0, "write": 1, "copy": 2, "gather19": 3}
@@ -102,6 +103,7 @@ def library():
         "lbm_macroscopic_device": [vp, vp],
         "lbm_init_equilibrium_device": [vp, vp],
         "lbm_mean_velocity": [vp, vp, P(d), P(d)],
+        "lbm_mean_velocity_static": [vp, vp, P(d), P(d)],
         "lbm_permeability": [vp, P(d), P(d), P(d)],
         "lbm_drag": [vp, vp],
         "lbm_set_delta_rho": [vp, d],
@@ -332,6 +334,16 @@ class Domain:
         vmax = C.c_double()
         tot = C.c_double()
         self._check(library().lbm_mean_velocity(self._h, _ptr(U), C.byref(vmax), C.byref(tot)))
+        return U, vmax.value, tot.value
+
+    def mean_velocity_static(self):
+        """mean_velocity through the no-allocation entry point (scratch in a
+        static device array of the library)."""
+        U = np.zeros(3)
+        vmax = C.c_double()
+        tot = C.c_double()
+        self._check(library().lbm_mean_velocity_static(self._h, _ptr(U), C.byref(vmax),
+                                                       C.byref(tot)))
         return U, vmax.value, tot.value
 
     def permeability(self):
