@@ -82,6 +82,39 @@ def test_stokes_permeability_16bit(case):
     assert abs(Kr / K64 - 1) > 1e-3
 
 
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_forchheimer_sweep_16bit_matches_oracle(storage):
+    """eq. (Forchheimer) in the reduced-precision mode against the FP64 oracle:
+    the three pressure drops of tests/golden/forchheimer_32cube.txt (32^3 cell,
+    sphere D = 20, TRT-CLI, Re_p 0.01 to 10), each run from rest with FP16 or
+    BF16 storage (stochastic rounding) until the residual falls below 1e-6 or
+    20 000 steps, then U averaged over 4 000 more steps (rounding noise keeps
+    the 16-bit residual near 1e-6, so U is a time average).  The fitted K_D
+    and beta are within 1e-3 of the oracle's fit (beta rests on the 0.01-3 %
+    inertial part of the pressure drop, so it is the harder of the two)."""
+    from paper_1508_02960_amd import observables as ob
+    from tests.golden import load_forchheimer_reference
+
+    ref = load_forchheimer_reference()
+    shape, D, tau = (32, 32, 32), 20.0, 0.8
+    U = []
+    for drho in ref["delta_rho"]:
+        d = lbm.Domain(shape, tau=tau, magic=3 / 16, delta_rho=float(drho), collision="trt",
+                       wall="cli", storage=storage, spheres=inputs.centred_sphere(shape, D))
+        d.run_to_residual(1e-6, 20000)
+        acc = []
+        for _ in range(200):
+            d.step(20)
+            acc.append(d.mean_velocity()[0][0])
+        d.close()
+        U.append(float(np.mean(acc)))
+    g = [ob.pressure_gradient(float(x), shape[2]) for x in ref["delta_rho"]]
+    K, beta, _ = ob.forchheimer_fit(g, U, tau)
+    assert abs(K / ref["K_D"] - 1) < 1e-3, K / ref["K_D"] - 1
+    assert abs(beta / ref["beta"] - 1) < 1e-3, beta / ref["beta"] - 1
+    assert np.max(np.abs(np.array(U) / ref["U"] - 1)) < 1e-3
+
+
 def test_stochastic_rounding_is_reproducible():
     shape = (16, 16, 24)
     sp = inputs.random_spheres(shape, 3, (2.0, 4.0), seed=91)
