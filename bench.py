@@ -208,7 +208,7 @@ def ceiling_leg(dev, edge: int, nbytes: int = 4 << 30, reps: int = 10):
     out["write"] = rate("write", None, b, nbytes, nbytes)
     out["copy"] = rate("copy", a, b, nbytes, 2 * nbytes)
     del a, b
-    n = edge - edge % 8
+    n = edge - edge % 16
     a = torch.full((19 * n ** 3,), 1e-3, dtype=torch.float32, device=dev)
     b = torch.zeros_like(a)
     out["gather19"] = rate("gather19", a, b, n, 2 * 19 * 4 * n ** 3)

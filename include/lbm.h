@@ -334,8 +334,8 @@ lbm_status lbm_destroy(lbm_domain d);
  *   LBM_PROBE_WRITE    writes n bytes to dst (src unused)
  *   LBM_PROBE_COPY     copies n bytes from src to dst
  *   LBM_PROBE_GATHER19 the step's pull pattern on an all-fluid periodic cube
- *                      of edge n (multiple of 8, at most 1024): src and dst
- *                      hold 19 FP32 planes of n^3 values in 8 x 8 tiles;
+ *                      of edge n (multiple of 16, at most 1024): src and dst
+ *                      hold 19 FP32 planes of n^3 values in 16 x 4 tiles;
  *                      reads and writes 2 * 76 n^3 bytes
  * Errors: LBM_ERR_INVALID_ARG for an unknown kind, a bad size, NULL or
  * misaligned buffers; LBM_ERR_DEVICE if the launch fails. */

@@ -53,7 +53,7 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
         f"{b.info.n_fluid} fluid cells")
     by, zp, ms = b.autotune(steps=10)
     sw = b.solid_writes
-    log(f"[batch] autotuned shape: rows/block {by}, z planes/block {zp}, solid writes {sw}, "
+    log(f"[batch] autotuned shape: wavefronts/block {by}, z planes/block {zp}, solid writes {sw}, "
         f"{ms:.3f} ms/step")
     t1 = time.perf_counter()
     b.run_to_residual(stokes_tol, max_steps)
@@ -79,7 +79,7 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     updates = float(np.sum(fluid * r["steps"]))
     re = [observables.reynolds_p(u[0], c["diameter"], c["tau"]) for u, c in zip(r["U"], cells)]
     out = dict(n_cells=n_cells, edge=edge, seed=seed, rejected=rejected, tol=tol,
-               max_steps=max_steps, shape=dict(rows_per_block=by, z_planes_per_block=zp,
+               max_steps=max_steps, shape=dict(waves_per_block=by, z_planes_per_block=zp,
                                                solid_writes=sw, ms_per_step_all_cells=ms),
                stokes_seconds=t_stokes, seconds=secs, status=st,
                mflups=updates / secs / 1e6,

@@ -13,8 +13,9 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Grid sizes measured best on MI355X for 8 GiB: reads peak with fewer,
-// longer-running workgroups, writes and copies with many.
+// The probes use the step kernel's instruction mix for large states: ordinary
+// loads and non-temporal stores.  Grid sizes measured best on MI355X for 8 GiB:
+// reads peak with fewer, longer-running workgroups, writes and copies with many.
 constexpr int kReadBlocks = 2048, kWriteBlocks = 32768, kThreads = 256;
 
 __global__ __launch_bounds__(kThreads) void read_kernel(const v4f* __restrict__ a, long long n4,
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(kThreads) void read_kernel(const v4f* __restrict__ 
   v4f s = {0.f, 0.f, 0.f, 0.f};
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n4;
        i += (long long)gridDim.x * kThreads)
-    s += __builtin_nontemporal_load(&a[i]);
+    s += a[i];
   const float t = (s.x + s.y) + (s.z + s.w);
   if (t == -1.2345e-30f) sink[0] = t;  // keeps the loads; the data never sum to this
 }
@@ -38,36 +39,39 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(const v4f* __restrict__ 
                                                         v4f* __restrict__ b, long long n4) {
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n4;
        i += (long long)gridDim.x * kThreads)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
+    __builtin_nontemporal_store(a[i], &b[i]);
 }
 
 // The step kernel's access pattern with nothing else: an all-fluid periodic
-// cube of edge n in 8 x 8 tiles (n a multiple of 8), 19 FP32 planes of n^3
-// values; dst[k](x) = src[k](x - e_k), workgroups of 16 wavefronts over
-// consecutive tiles of a z plane, non-temporal stores.
+// cube of edge n in the step's layout for large states (16 x 4 tiles, n a
+// multiple of 16), 19 FP32 planes of n^3 values; dst[k](x) = src[k](x - e_k),
+// workgroups of 8 wavefronts over consecutive tiles of a z plane,
+// non-temporal stores.
 __constant__ int kEx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 __constant__ int kEy[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
 __constant__ int kEz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
 
-__device__ __forceinline__ int tiled(int x, int y, int z, int ntx, int plane) {
-  return (((x >> 3) + ntx * (y >> 3)) << 6) + ((y & 7) << 3) + (x & 7) + z * plane;
-}
+__device__ __forceinline__ int xpart(int x) { return ((x >> 4) << 6) | (x & 15); }
+__device__ __forceinline__ int ypart(int y, int ntx) { return (y >> 2) * (ntx << 6) + ((y & 3) << 4); }
 
-__global__ __launch_bounds__(1024) void gather19_kernel(const float* __restrict__ src,
-                                                        float* __restrict__ dst, int n) {
-  const int ntx = n >> 3, plane = n * n;
+__global__ __launch_bounds__(512) void gather19_kernel(const float* __restrict__ src,
+                                                       float* __restrict__ dst, int n) {
+  const int ntx = n >> 4, nty = n >> 2, plane = n * n;
   const int tile = blockIdx.x * blockDim.y + threadIdx.y;
-  if (tile >= ntx * ntx) return;
+  if (tile >= ntx * nty) return;
   const int l = threadIdx.x;
-  const int x = ((tile % ntx) << 3) + (l & 7), y = ((tile / ntx) << 3) + (l >> 3), z = blockIdx.z;
+  const int x = ((tile % ntx) << 4) + (l & 15), y = ((tile / ntx) << 2) + (l >> 4), z = blockIdx.z;
   const long long st = (long long)plane * n;
-  const int c = tiled(x, y, z, ntx, plane);
+  // wrapped neighbour coordinates as address parts (index 0: -1, 1: 0, 2: +1)
+  const int xs[3] = {xpart(x == 0 ? n - 1 : x - 1), xpart(x), xpart(x == n - 1 ? 0 : x + 1)};
+  const int ys[3] = {ypart(y == 0 ? n - 1 : y - 1, ntx), ypart(y, ntx),
+                     ypart(y == n - 1 ? 0 : y + 1, ntx)};
+  const int zs[3] = {(z == 0 ? n - 1 : z - 1) * plane, z * plane, (z == n - 1 ? 0 : z + 1) * plane};
+  const int c = xs[1] + ys[1] + zs[1];
   float v[19];
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const int sx = (x - kEx[k] + n) % n, sy = (y - kEy[k] + n) % n, sz = (z - kEz[k] + n) % n;
-    v[k] = src[k * st + tiled(sx, sy, sz, ntx, plane)];
-  }
+  for (int k = 0; k < 19; ++k)
+    v[k] = src[k * st + xs[1 - kEx[k]] + ys[1 - kEy[k]] + zs[1 - kEz[k]]];
 #pragma unroll
   for (int k = 0; k < 19; ++k) __builtin_nontemporal_store(v[k], &dst[k * st + c]);
 }
@@ -92,9 +96,9 @@ LBM_API lbm_status lbm_bandwidth_probe(int32_t kind, const void* src, void* dst,
       copy_kernel<<<kWriteBlocks, kThreads, 0, s>>>((const v4f*)src, (v4f*)dst, n / 16);
       break;
     case LBM_PROBE_GATHER19: {
-      if (!src || !dst || n < 8 || n % 8 || n > 1024 || !a16) return LBM_ERR_INVALID_ARG;
-      const int e = (int)n, tiles = (e / 8) * (e / 8);
-      gather19_kernel<<<dim3((tiles + 15) / 16, 1, e), dim3(64, 16), 0, s>>>(
+      if (!src || !dst || n < 16 || n % 16 || n > 1024 || !a16) return LBM_ERR_INVALID_ARG;
+      const int e = (int)n, tiles = (e / 16) * (e / 4);
+      gather19_kernel<<<dim3((tiles + 7) / 8, 1, e), dim3(64, 8), 0, s>>>(
           (const float*)src, (float*)dst, e);
       break;
     }

@@ -6,8 +6,8 @@ sweep test.  Calls only the oracle.
     python tests/golden/make_forchheimer_reference.py
 
 Cell: 32^3 with a centred sphere of diameter 20, TRT (Lambda = 3/16, tau =
-0.8), CLI walls.  Pressure drops from the Darcy estimate for Re_p = 0.01, 2 and
-10 with a permeability guess of 80: delta_rho = 3 nx nu^2 Re / (D K)
+0.8), CLI walls.  Pressure drops from the Darcy estimate for Re_p = 0.01, 3 and
+15 with a permeability guess of 40: delta_rho = 3 nx nu^2 Re / (D K)
 (U = Re nu / D, grad p = nu U / K, dp = delta_rho / 3).  Each run starts at
 rest and stops when the relative change of U over 100 steps stays below
 1e-10 three times in a row.  Fit: grad p / U = nu / K_D + beta U by least
@@ -24,8 +24,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 
 EDGE, D, TAU, MAGIC = 32, 20.0, 0.8, 3 / 16
-RE = (0.01, 2.0, 10.0)
-K_GUESS = 80.0
+RE = (0.01, 3.0, 15.0)
+K_GUESS = 40.0
 
 
 def main() -> None:

@@ -86,12 +86,14 @@ def test_stokes_permeability_16bit(case):
 def test_forchheimer_sweep_16bit_matches_oracle(storage):
     """eq. (Forchheimer) in the reduced-precision mode against the FP64 oracle:
     the three pressure drops of tests/golden/forchheimer_32cube.txt (32^3 cell,
-    sphere D = 20, TRT-CLI, Re_p 0.01 to 10), each run from rest with FP16 or
-    BF16 storage (stochastic rounding) until the residual falls below 1e-6 or
-    20 000 steps, then U averaged over 4 000 more steps (rounding noise keeps
-    the 16-bit residual near 1e-6, so U is a time average).  The fitted K_D
-    and beta are within 1e-3 of the oracle's fit (beta rests on the 0.01-3 %
-    inertial part of the pressure drop, so it is the harder of the two)."""
+    sphere D = 20, TRT-CLI, Re_p 0.01, 3 and 15), each run from rest with FP16
+    or BF16 storage (stochastic rounding) until the residual falls below 1e-6
+    or 20 000 steps, then U averaged over 60 000 more steps.  Rounding noise
+    keeps the 16-bit U fluctuating by 1e-5 (FP16) to 1e-4 (BF16) from step to
+    step, with a correlation time of a few thousand steps, so U is a time
+    average.  beta rests on the inertial part of the pressure drop (about 4 %
+    at Re_p = 15): an error e in U_3 - U_2 becomes about 30 e in beta.  The
+    fitted K_D and beta are within 1e-3 of the oracle's fit."""
     from paper_1508_02960_amd import observables as ob
     from tests.golden import load_forchheimer_reference
 
@@ -103,8 +105,8 @@ def test_forchheimer_sweep_16bit_matches_oracle(storage):
                        wall="cli", storage=storage, spheres=inputs.centred_sphere(shape, D))
         d.run_to_residual(1e-6, 20000)
         acc = []
-        for _ in range(200):
-            d.step(20)
+        for _ in range(3000):
+            d.run_to_residual(0.0, 20)  # 20 steps; FP16 moves its scale if needed
             acc.append(d.mean_velocity()[0][0])
         d.close()
         U.append(float(np.mean(acc)))
