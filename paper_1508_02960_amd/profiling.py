@@ -85,7 +85,9 @@ def traffic(fetch, write, probe_bytes, kernel, workload, n_fluid, bpu, out_md, o
     lines = [f"# HBM traffic of `{kernel}` ({workload})", "",
              f"Command (run twice, with `--pmc FETCH_SIZE` and with `--pmc WRITE_SIZE`): "
              f"`{command}`", "",
-             "Counters are KiB per dispatch.  They are scaled by what the same counters read for "
+             "Counters are KiB per dispatch of requests from the L2 caches to the memory side, "
+             "which includes hits in the last-level (Infinity) cache, so they bound the HBM "
+             "traffic from above.  They are scaled by what the same counters read for "
              f"the bandwidth probes of {int(nb)} bytes in the same runs: FETCH_SIZE x{f_factor:.3f} "
              f"(read probe), WRITE_SIZE x{w_factor:.3f} (write probe).  Check on the copy probe "
              f"(reads and writes {int(nb)} bytes): scaled reads {copy_read:.3f}x, scaled writes "
@@ -95,7 +97,7 @@ def traffic(fetch, write, probe_bytes, kernel, workload, n_fluid, bpu, out_md, o
              f"| WRITE_SIZE (raw KiB) | {wm[kernel]:.1f} |",
              f"| read bytes (scaled) | {kf / 1e6:.2f} MB |",
              f"| written bytes (scaled) | {kw / 1e6:.2f} MB |",
-             f"| total HBM traffic | {(kf + kw) / 1e6:.2f} MB |",
+             f"| total memory-side traffic (HBM and last-level-cache hits) | {(kf + kw) / 1e6:.2f} MB |",
              f"| algorithmic bytes ({n_fluid} fluid cells x {bpu} B) | {alg / 1e6:.2f} MB |",
              f"| reads / algorithmic reads | {kf / (alg / 2):.3f} |",
              f"| writes / algorithmic writes | {kw / (alg / 2):.3f} |",
