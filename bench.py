@@ -68,8 +68,9 @@ def workload_spheres(shape, dia):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_1508_02960_amd.profiling import kernel_source_hash as h
+
+    return h()
 
 
 def stored_traffic(workload: str, n_fluid: int):

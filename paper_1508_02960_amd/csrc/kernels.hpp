@@ -766,8 +766,9 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
 // The 19 values a solid cell writes: its wall-link slots (flag bit k: the
 // slot in plane k is pulled by the fluid node c + e_k and holds that link's
 // coefficient) are copied, every other slot is zero.  In batches, solid
-// cells next to fluid cells along x may write so that the lines the fluid
-// cells write are written whole: where sphere surfaces cut many lines,
+// cells that share a tile or a line with fluid cells may write so that the
+// lines the fluid cells write are written whole: where sphere surfaces cut
+// many lines,
 // partly written lines cost far more than their bytes (a batch of 64^3 cells
 // holding spheres of diameter 50 steps 17% faster with mode 1).
 template <typename S>
@@ -781,8 +782,9 @@ __device__ __forceinline__ void solid_node(const S* __restrict__ src, S (&out)[k
 
 // Whether this lane stores, given the fluid lanes of its wavefront: fluid
 // lanes always; solid lanes never (mode 0), when the wavefront holds a fluid
-// cell (mode 1), or when their 128-byte line of a plane does (mode 2: lanes
-// [g, g + L) of a wavefront along x share a line, L = 128 / sizeof(S)).
+// cell (mode 1), or when their 128-byte line of a plane does (mode 2: the
+// lanes of a wavefront hold 64 consecutive addresses, so lanes [g, g + L)
+// share a line, L = 128 / sizeof(S)).
 template <typename S>
 __device__ __forceinline__ bool solid_stores(int mode, bool solid, unsigned long long fluid) {
   if (!solid) return true;

@@ -23,8 +23,15 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hpp")
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the step kernels' source with comments and blank space
+    removed, so that counters stay attached to the code they measured."""
+    import re
+
+    src = open(KERNEL_SOURCE).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = "\n".join(line.strip() for line in src.splitlines() if line.strip())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def short_name(full: str) -> str:

@@ -431,6 +431,57 @@ def linear_density(shape, delta_rho: float, fluid):
     return np.where(fluid, -(delta_rho / nx) * x, 0.0)
 
 
+# ------------------------------------------------------ two-grid start
+# A cell larger than the network's receptive field (about 54 nodes) is
+# predicted on the grid of half the resolution instead: coarse node j sits at
+# fine position 2j + 1/2, the centre of a 2 x 2 x 2 block of fine nodes, so
+# the coarse pack is the same spheres in units of two fine cells.  The
+# prediction is interpolated back to the fine nodes.
+
+def coarse_fluid(spheres, edge: int) -> np.ndarray:
+    """Fluid mask (edge/2)^3 of a periodic pack of spheres (rows cx, cy, cz,
+    r in fine lattice units, box edge `edge`) on the coarse grid: a coarse
+    node is solid iff its position lies strictly inside a sphere or one of its
+    periodic images."""
+    ec = edge // 2
+    pos = 2.0 * np.arange(ec) + 0.5
+    solid = np.zeros((ec, ec, ec), bool)
+    for cx, cy, cz, r in np.reshape(spheres, (-1, 4)):
+        per = []
+        for v in (cz, cy, cx):
+            a = np.abs(pos - v)
+            per.append(np.minimum(a, edge - a) ** 2)
+        solid |= per[0][:, None, None] + per[1][None, :, None] + per[2][None, None, :] < r * r
+    return ~solid
+
+
+def prolongate2(t: np.ndarray) -> np.ndarray:
+    """Coarse targets (ec, ec, ec, C) -> fine (2ec, 2ec, 2ec, C): periodic
+    trilinear interpolation at the fine nodes, which sit at coarse
+    coordinates (i - 1/2)/2, so each fine node takes 3/4 of its nearer and
+    1/4 of its farther coarse neighbour per axis.  Lengths double on the fine
+    grid: velocity targets (length^2) are multiplied by 4, density targets
+    (length) by 2."""
+    out = np.asarray(t, np.float64)
+    for ax in range(3):
+        even = 0.75 * out + 0.25 * np.roll(out, 1, axis=ax)   # fine 2m: between m-1 and m
+        odd = 0.75 * out + 0.25 * np.roll(out, -1, axis=ax)   # fine 2m+1: between m and m+1
+        shape = list(out.shape)
+        shape[ax] *= 2
+        fine = np.empty(shape)
+        sl_e = [slice(None)] * 4
+        sl_o = [slice(None)] * 4
+        sl_e[ax] = slice(0, None, 2)
+        sl_o[ax] = slice(1, None, 2)
+        fine[tuple(sl_e)] = even
+        fine[tuple(sl_o)] = odd
+        out = fine
+    scale = np.ones(out.shape[-1])
+    scale[:3] = 4.0
+    scale[3:] = 2.0
+    return (out * scale).astype(np.float32)
+
+
 _D3Q19_NEIGHBOURS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
                      if 0 < abs(dz) + abs(dy) + abs(dx) <= 2]
 

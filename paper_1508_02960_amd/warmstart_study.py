@@ -236,7 +236,7 @@ def _trajectory(b, start, chunk, n_chunks):
 
 def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
              device=None, log=_log, chunk: int = 0, n_chunks: int = 0,
-             with_density: bool = False, controls: bool = True):
+             with_density: bool = False, controls: bool = True, two_grid: bool = False):
     """Starts of the same packs, each run to tol by the plain iteration:
     rest; linear density; the network's velocity (wall layer at rest) with
     the linear density; with with_density the same plus the network's
@@ -246,7 +246,10 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
     chunk > 0, |U_x / U_x* - 1| every chunk steps for each start.  nets is
     a network or a dict name -> network; the starts of a network named n
     are network_u[n] and network_u_rho[n] (no suffix for a single one).
-    controls=False runs only the rest and network starts."""
+    controls=False runs only the rest and network starts.  With two_grid
+    each network also predicts on the half-resolution grid of every pack
+    (warmstart.coarse_fluid), and the prediction interpolated back
+    (warmstart.prolongate2) is the start network_u_2grid[n]."""
     if not isinstance(nets, dict):
         nets = {"": nets}
     cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
@@ -267,6 +270,14 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
             preds[tag] = pred
             wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
             starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
+            if two_grid:
+                t0 = time.perf_counter()
+                pc = np.stack([W.prolongate2(net.predict(W.coarse_fluid(sp, edge)))
+                               for sp, _ in packs])
+                out["predict_seconds_2grid" + tag] = time.perf_counter() - t0
+                preds["_2grid" + tag] = pc
+                wu = [W.warm_fields(pc[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
+                starts["network_u_2grid" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
             if with_density:
                 wr = [W.warm_fields(pred[i], delta_rho, tau, fluid[i], use_density=True)
                       for i in range(len(packs))]
@@ -298,7 +309,7 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
         if chunk > 0:
             Ustar = np.array(out["rest"]["U"])
             for name in ["rest"] + (["converged_fields"] if controls else []) + [
-                    "network_u" + t for t in nets]:
+                    n for n in starts if n.startswith("network_u") and "rho" not in n]:
                 st = conv if name == "converged_fields" else starts[name]
                 traj = _trajectory(b, st, chunk, n_chunks)
                 out[name]["trajectory_rel_error"] = np.abs(traj / Ustar[None] - 1).tolist()
@@ -347,6 +358,8 @@ def main(argv=None) -> int:
     ev.add_argument("--weights", required=True, nargs="+",
                     help="network weights, as path or name=path")
     ev.add_argument("--with-density", action="store_true")
+    ev.add_argument("--two-grid", action="store_true",
+                    help="also start from each network's half-resolution prediction")
     ev.add_argument("--spheres", default="8,27", help="sphere count range per cell")
     ev.add_argument("--cells", type=int, default=64)
     ev.add_argument("--edge", type=int, default=128)
@@ -407,7 +420,7 @@ def main(argv=None) -> int:
         packs = draw_packs(a.cells, a.edge, a.seed, tuple(int(v) for v in a.spheres.split(",")))
         res = evaluate(nets, packs, a.edge, tau=a.tau, delta_rho=a.delta_rho, tol=a.tol,
                        max_steps=a.max_steps, chunk=a.chunk, n_chunks=a.n_chunks,
-                       with_density=a.with_density)
+                       with_density=a.with_density, two_grid=a.two_grid)
         res["params"] = {k: n.n_params() for k, n in nets.items()}
         with open(a.out, "w") as fh:
             json.dump(res, fh, indent=1)

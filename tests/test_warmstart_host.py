@@ -59,3 +59,44 @@ def test_target_units_round_trip():
     G = 2e-5 / 3 / 10
     nu = (0.9 - 0.5) / 3
     assert np.allclose(t[..., 0], np.where(fluid, u[0] * nu / G, 0), rtol=1e-6)
+
+
+def test_coarse_fluid_is_the_pack_at_half_resolution():
+    """Coarse node j sits at fine position 2j + 1/2 and is solid iff that
+    point lies strictly inside a sphere or a periodic image (brute force)."""
+    from paper_1508_02960_amd import warmstart as W
+
+    rng = np.random.default_rng(3)
+    edge = 16
+    sp = np.hstack([rng.uniform(0, edge, (3, 3)), rng.uniform(1.5, 4.0, (3, 1))])
+    got = W.coarse_fluid(sp, edge)
+    ec = edge // 2
+    want = np.ones((ec, ec, ec), bool)
+    for z in range(ec):
+        for y in range(ec):
+            for x in range(ec):
+                p = np.array([2 * x + 0.5, 2 * y + 0.5, 2 * z + 0.5])
+                for cx, cy, cz, r in sp:
+                    for o in np.ndindex(3, 3, 3):
+                        c = np.array([cx, cy, cz]) + (np.array(o) - 1) * edge
+                        if np.sum((p - c) ** 2) < r * r:
+                            want[z, y, x] = False
+    assert np.array_equal(got, want)
+
+
+def test_prolongate2_interpolates_linear_fields_and_scales_lengths():
+    """Trilinear interpolation at fine nodes (coarse coordinate (i - 1/2)/2)
+    is exact for a field linear in each coordinate away from the periodic
+    seam; velocity targets scale by 4 (length^2), density targets by 2."""
+    from paper_1508_02960_amd import warmstart as W
+
+    ec = 6
+    z, y, x = np.meshgrid(np.arange(ec), np.arange(ec), np.arange(ec), indexing="ij")
+    t = np.stack([x + 2.0 * y, 3.0 * z, np.ones_like(x, float), 1.0 * x - z], axis=-1)
+    f = W.prolongate2(t)
+    assert f.shape == (2 * ec, 2 * ec, 2 * ec, 4)
+    fz, fy, fx = np.meshgrid(*(np.arange(2 * ec),) * 3, indexing="ij")
+    cz, cy, cx = (fz - 0.5) / 2, (fy - 0.5) / 2, (fx - 0.5) / 2
+    inner = (fz > 0) & (fz < 2 * ec - 1) & (fy > 0) & (fy < 2 * ec - 1) & (fx > 0) & (fx < 2 * ec - 1)
+    want = np.stack([4 * (cx + 2 * cy), 4 * 3 * cz, 4 * np.ones_like(cx), 2 * (cx - cz)], axis=-1)
+    assert np.allclose(f[inner], want[inner], atol=1e-5)
