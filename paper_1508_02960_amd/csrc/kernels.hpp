@@ -532,15 +532,14 @@ __device__ __forceinline__ void stored_moments(const S* __restrict__ src, long l
 // and QIBB with q >= 1/2 keep LIBB's q >= 1/2 branch, which needs x_f1
 // only); x_f3 solid -> LIBB (from QIBB) or CLI (from MR).  Unscaled storage
 // (FP32, FP64) only.  m1 holds the density deviation and velocity of the
-// stored state at x (IEBB only; the caller computes them once per node).
+// stored state at x (IEBB only), own_j and own_k the stored g_j and g_k at x
+// (the caller loads them once per node).
 template <typename S, typename C>
 __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __restrict__ flags,
                                 const StepParams& p, int x, int y, int z, int c, int k, C q,
-                                uint32_t fl, const C (&m1)[4], C pulled_j) {
+                                uint32_t fl, const C (&m1)[4], C pulled_j, C own_j, C own_k) {
   const long long st = p.stride;
   const int j = kLat.opp[k];
-  const C own_j = (C)Storage<S>::to_float(src[j * st + c]);
-  const C own_k = (C)Storage<S>::to_float(src[k * st + c]);
   const FarNode n2 = far_node(p, x, y, z, k, 1);
   const FarNode n3 = far_node(p, x, y, z, k, 2);
   // x_f2 = x - e_j is the pull source of direction j here, and x_f3 that of
@@ -658,32 +657,36 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
   // wall links: the pulled raw value is the stored coefficient a (CLI) or
   // the wall distance q (general rules)
   if (fl & kLinkMask) {
+    // The node's own stored values of every moving direction (the wall rules
+    // need g_j and g_k at x), all requested before the first use: one memory
+    // round trip per boundary node instead of one per link direction (512^3
+    // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
+    // come from the same values.
+    S own[kQ];
+#pragma unroll
+    for (int k = 1; k < kQ; ++k) own[k] = src[k * st + c];
     C m1[4] = {(C)0, (C)0, (C)0, (C)0};
     if constexpr (WALL == kGEN) {
       if (p.wall == kRuleIEBB) {
-        C u1[3];
-        stored_moments<S, C>(src, st, c, m1[0], u1);
-        m1[1] = u1[0];
-        m1[2] = u1[1];
-        m1[3] = u1[2];
-      }
-    }
-    // The node's own stored values of every moving direction (bounce-back
-    // and CLI need g_j and g_k at x), all requested before the first use:
-    // one memory round trip per boundary node instead of one per link
-    // direction (512^3 sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).
-    S own[kQ];
-    if constexpr (WALL != kGEN) {
+        own[0] = src[c];
 #pragma unroll
-      for (int k = 1; k < kQ; ++k) own[k] = src[k * st + c];
+        for (int kk = 0; kk < kQ; ++kk) {
+          const C v = (C)St::to_float(own[kk]);
+          m1[0] += v;
+          m1[1] += (C)kLat.ex[kk] * v;
+          m1[2] += (C)kLat.ey[kk] * v;
+          m1[3] += (C)kLat.ez[kk] * v;
+        }
+      }
     }
 #pragma unroll
     for (int k = 1; k < kQ; ++k) {
       if (fl & (1u << k)) {
         if constexpr (WALL == kGEN) {
           // the pulled raw value is the link's wall distance q
-          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1,
-                                                 g[kLat.opp[k]]);
+          const int j = kLat.opp[k];
+          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1, g[j],
+                                          (C)St::to_float(own[j]), (C)St::to_float(own[k]));
           continue;
         }
         const int j = kLat.opp[k];
@@ -1164,7 +1167,9 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
         const double q = (double)Storage<S>::to_float(src[k * st + p.t.at(sx, sy, sz)]);
         const FarNode n2 = far_node(p, x, y, z, k, 1);
         back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1,
-                                             (double)Storage<S>::to_float(src[j * st + n2.c]));
+                                             (double)Storage<S>::to_float(src[j * st + n2.c]),
+                                             (double)Storage<S>::to_float(src[j * st + c]),
+                                             (double)Storage<S>::to_float(src[k * st + c]));
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;

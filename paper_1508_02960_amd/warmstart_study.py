@@ -236,7 +236,8 @@ def _trajectory(b, start, chunk, n_chunks):
 
 def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float, max_steps: int,
              device=None, log=_log, chunk: int = 0, n_chunks: int = 0,
-             with_density: bool = False, controls: bool = True, two_grid: bool = False):
+             with_density: bool = False, controls: bool = True, two_grid: bool = False,
+             direct: bool = True):
     """Starts of the same packs, each run to tol by the plain iteration:
     rest; linear density; the network's velocity (wall layer at rest) with
     the linear density; with with_density the same plus the network's
@@ -249,7 +250,8 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
     controls=False runs only the rest and network starts.  With two_grid
     each network also predicts on the half-resolution grid of every pack
     (warmstart.coarse_fluid), and the prediction interpolated back
-    (warmstart.prolongate2) is the start network_u_2grid[n]."""
+    (warmstart.prolongate2) is the start network_u_2grid[n]; direct=False
+    then leaves out the full-resolution starts."""
     if not isinstance(nets, dict):
         nets = {"": nets}
     cells = [dict(spheres=sp, tau=tau, magic=3 / 16, delta_rho=delta_rho) for sp, _ in packs]
@@ -264,12 +266,14 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
             starts["linear_density"] = (lin, None)
         preds = {}
         for tag, net in nets.items():
-            t0 = time.perf_counter()
-            pred = np.stack([net.predict(fluid[i]) for i in range(len(packs))])
-            out["predict_seconds" + tag] = time.perf_counter() - t0
-            preds[tag] = pred
-            wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
-            starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
+            if direct or not two_grid:
+                t0 = time.perf_counter()
+                pred = np.stack([net.predict(fluid[i]) for i in range(len(packs))])
+                out["predict_seconds" + tag] = time.perf_counter() - t0
+                preds[tag] = pred
+                wu = [W.warm_fields(pred[i], delta_rho, tau, fluid[i])
+                      for i in range(len(packs))]
+                starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
             if two_grid:
                 t0 = time.perf_counter()
                 pc = np.stack([W.prolongate2(net.predict(W.coarse_fluid(sp, edge)))
@@ -278,8 +282,8 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
                 preds["_2grid" + tag] = pc
                 wu = [W.warm_fields(pc[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
                 starts["network_u_2grid" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
-            if with_density:
-                wr = [W.warm_fields(pred[i], delta_rho, tau, fluid[i], use_density=True)
+            if with_density and tag in preds:
+                wr = [W.warm_fields(preds[tag][i], delta_rho, tau, fluid[i], use_density=True)
                       for i in range(len(packs))]
                 starts["network_u_rho" + tag] = (np.stack([w[0] for w in wr]),
                                                  np.stack([w[1] for w in wr], axis=1))
