@@ -34,7 +34,6 @@ sys.path.insert(0, ROOT)
 METRIC = "D3Q19 TRT MLUPS + %HBM roofline; time-to-steady-state (plain vs warm-start)"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1508_02960_amd", "csrc", "kernels.hpp")
 
 WORKLOADS = {
     # name: (shape, sphere diameter, collision, wall, storage, tau, magic, delta_rho)
@@ -77,15 +76,16 @@ def kernel_source_hash() -> str:
     return h()
 
 
-def stored_traffic(workload: str, n_fluid: int):
+def stored_traffic(kernel: str, workload: str):
     """HBM bytes per step-kernel launch from committed rocprofv3 counters, or
     None if they were taken on a different kernel source or workload."""
     try:
-        with open(os.path.join(PROFILES, f"step_kernel_{workload}_traffic.json")) as f:
+        with open(os.path.join(PROFILES, f"{kernel}_{workload}_traffic.json")) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("workload") != workload:
+    if (t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("kernel") != kernel):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -264,6 +264,8 @@ def main() -> int:
                    check_interval=100)
     n_fluid, n_cells = d.n_fluid, d.ncell
     stream = d.stream
+    # the step kernel this shape launches (two cells per lane for large 16-bit states)
+    kernel = "step_pair_kernel" if d.step_shape()[1] else "step_kernel"
     print(f"[bench] workload {args.workload}: {n_cells} cells, {n_fluid} fluid, "
           f"{d.info.n_links} links, workspace {d.info.workspace_bytes / 2**30:.2f} GiB",
           file=sys.stderr, flush=True)
@@ -305,7 +307,7 @@ def main() -> int:
     bpu = int(d.info.bytes_per_fluid_update)
     alg_bytes = n_fluid * bpu
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, n_fluid)
+    traffic = stored_traffic(kernel, args.workload)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -338,7 +340,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "step_kernel",
+            "kernel": kernel,
             "kernel_ms": round(kernel_ms, 6),
             "algorithmic_bytes_per_launch": alg_bytes,
             "bytes_per_fluid_update": bpu,

@@ -129,6 +129,8 @@ typedef struct {
   double omega_minus;      /* TRT antisymmetric rate from Lambda                */
   int64_t bytes_per_fluid_update; /* algorithmic HBM bytes per fluid-cell update */
   double storage_scale;    /* sigma of 16-bit storage (1 otherwise)             */
+  int32_t tile_width;      /* cells: the device buffers' tiles (x extent)       */
+  int32_t tile_height;     /* cells: the tiles' y extent (width * height = 64)  */
 } lbm_info;
 
 /* Create a domain on the host (no device work).  Sec. 3 / Sec. 2.2.1.
@@ -180,6 +182,17 @@ lbm_status lbm_get_state(lbm_domain d, double* g);
  * eq. (collision)) with the wall rule and the periodic pressure drop.
  * Asynchronous; n = 0 is a no-op. */
 lbm_status lbm_step(lbm_domain d, int64_t n);
+
+/* Launch shape of the single-domain step: wavefronts per workgroup (waves:
+ * 1, 2, 4, 8 or 16) and whether 16-bit storage steps two x-adjacent cells
+ * per lane (pairs 1) or one (pairs 0).  Results do not depend on the shape
+ * (the stored state is the same bit for bit); only the speed does.  The
+ * library picks a shape at lbm_bind; this call overrides it (for tuning and
+ * tests).  pairs 1 needs FP16/BF16 storage and nx a multiple of the tile
+ * width that lbm_get_info reports.  LBM_ERR_INVALID_ARG otherwise, or for a
+ * batch. */
+lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t pairs);
+lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* pairs);
 
 /* Step until the relative change of the superficial mean velocity U_x over
  * check_interval steps stays below tol for three checks in a row (stopping

@@ -13,12 +13,16 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["lbm.hip", "geometry.cpp", "nn.hip", "ceiling.hip"]
+SOURCES = ["lbm.hip", "step_f64.hip", "step_f32.hip", "step_f16.hip", "step_bf16.hip",
+           "geometry.cpp", "nn.hip", "ceiling.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
+# -ffp-contract=on: a multiply and an add fuse only within one source
+# expression, so the same source computes the same bits in every kernel that
+# inlines it (the one-cell and two-cell step kernels store identical states).
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
+    "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

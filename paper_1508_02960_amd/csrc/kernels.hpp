@@ -203,8 +203,9 @@ struct IsStochastic<bf16s_t> {
   static constexpr bool value = true;
 };
 
-// Counter-based random word for (cell, direction, step seed): a 32-bit
-// integer finaliser (xor-shift / multiply rounds).
+// Counter-based random word for (cell, direction, step seed): C. Wellons'
+// published "lowbias32" 32-bit integer hash (two xor-shift / multiply
+// rounds, public domain).
 __device__ __host__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -546,7 +547,10 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
   // direction j at x_f2, so the flag bits j of x and of x_f2 tell if they
   // are solid
   const bool f2 = !(fl & (1u << j));
-  const bool f3 = f2 && !(flags[n2.c] & (1u << j));
+  int rule = p.wall;
+  // x_f3's flag word is read only by the rules that use x_f3
+  const bool wants_f3 = rule == kRuleMR || (rule == kRuleQIBB && q < (C)0.5);
+  const bool f3 = f2 && wants_f3 && !(flags[n2.c] & (1u << j));
   // g_j at x_f2 is this node's pull in direction j (pulled_j, raw); with the
   // jump of a read across the x-periodic plane
   C f2_j = pulled_j;
@@ -555,7 +559,6 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
     if (n2.cross > 0) f2_j -= jw;
     if (n2.cross < 0) f2_j += jw;
   }
-  int rule = p.wall;
   if (rule == kRuleMR && !f3) rule = kRuleCLI;
   if (rule == kRuleQIBB && (q < (C)0.5 ? !f3 : !f2)) rule = kRuleLIBB;
   const C one = (C)1, two = (C)2;
@@ -614,30 +617,21 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
 }
 
 
-// One time step for the node (x, y, z), fluid, with flag word fl: pull,
-// wall rule, pressure jump, collision, and the 19 values to store (out, in
-// the storage format; the caller stores them).  Returns the pre-collision
-// moments (which the collision conserves) and max_k |g*_k| / w_k of the
-// stored result, for the optional reduction.
+// The part of a node's time step after the pull: SBB / CLI wall links (the
+// general rules are applied by the caller), pressure jump, collision, and the
+// 19 values to store (out, in the storage format).  g holds the pulled raw
+// stored values (on a wall link: the stored coefficient a for CLI); own holds
+// the node's own stored values of directions 1..18 when it has wall links.
+// Returns the pre-collision moments (which the collision conserves) and
+// max_k |g*_k| / w_k of the stored result, for the optional reduction.
 template <typename S, int COLL, int WALL>
-__device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[kQ],
-                                            const uint32_t* __restrict__ flags,
-                                            const StepParams& p, int x, int y, int z, int c,
-                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
+__device__ __forceinline__ void finish_node(typename ComputeOf<S>::type (&g)[kQ],
+                                            const S (&own)[kQ], S (&out)[kQ],
+                                            const StepParams& p, int x, int c, uint32_t fl,
+                                            typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
   using St = Storage<S>;
-  const int nx = p.nx, plane = p.t.plane;
-  Nbr n;
-  n.xs[0] = p.t.xpart(x == 0 ? nx - 1 : x - 1);
-  n.xs[1] = p.t.xpart(x);
-  n.xs[2] = p.t.xpart(x == nx - 1 ? 0 : x + 1);
-  n.ys[0] = p.t.ypart(y == 0 ? p.ny - 1 : y - 1);
-  n.ys[1] = p.t.ypart(y);
-  n.ys[2] = p.t.ypart(y == p.ny - 1 ? 0 : y + 1);
-  n.zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
-  n.zs[1] = z * plane;
-  n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
-
+  const int nx = p.nx;
   // stored -> g factors per weight class (1 for unscaled storage)
   C dec[3] = {(C)1, (C)1, (C)1};
   if constexpr (St::scaled) {
@@ -646,64 +640,27 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
     dec[1] = (C)(kLat.w[1] * is);
     dec[2] = (C)(kLat.w[7] * is);
   }
-
-  const long long st = p.stride;
-  C g[kQ];
-  // pull: direction k arrives from x - e_k (raw stored values)
+  if constexpr (WALL != kGEN) {
+    if (fl & kLinkMask) {
 #pragma unroll
-  for (int k = 0; k < kQ; ++k)
-    g[k] = (C)St::to_float(src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])]);
-
-  // wall links: the pulled raw value is the stored coefficient a (CLI) or
-  // the wall distance q (general rules)
-  if (fl & kLinkMask) {
-    // The node's own stored values of every moving direction (the wall rules
-    // need g_j and g_k at x), all requested before the first use: one memory
-    // round trip per boundary node instead of one per link direction (512^3
-    // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
-    // come from the same values.
-    S own[kQ];
-#pragma unroll
-    for (int k = 1; k < kQ; ++k) own[k] = src[k * st + c];
-    C m1[4] = {(C)0, (C)0, (C)0, (C)0};
-    if constexpr (WALL == kGEN) {
-      if (p.wall == kRuleIEBB) {
-        own[0] = src[c];
-#pragma unroll
-        for (int kk = 0; kk < kQ; ++kk) {
-          const C v = (C)St::to_float(own[kk]);
-          m1[0] += v;
-          m1[1] += (C)kLat.ex[kk] * v;
-          m1[2] += (C)kLat.ey[kk] * v;
-          m1[3] += (C)kLat.ez[kk] * v;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 1; k < kQ; ++k) {
-      if (fl & (1u << k)) {
-        if constexpr (WALL == kGEN) {
-          // the pulled raw value is the link's wall distance q
+      for (int k = 1; k < kQ; ++k) {
+        if (fl & (1u << k)) {
           const int j = kLat.opp[k];
-          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1, g[j],
-                                          (C)St::to_float(own[j]), (C)St::to_float(own[k]));
-          continue;
-        }
-        const int j = kLat.opp[k];
-        const C own_j = (C)St::to_float(own[j]) * dec[wclass(j)];
-        if constexpr (WALL == kCLI) {
-          const C a = g[k];
-          const C own_k = (C)St::to_float(own[k]) * dec[wclass(k)];
-          // g_j at the second node x_f2 = x + e_k (away from the wall) is what
-          // this node pulls in direction j, so g[j] already holds it (raw); it
-          // is read across the x-periodic plane with the pressure jump.  If
-          // x_f2 is solid, g[j] is a coefficient and a = 0.
-          C far_j = g[j] * dec[wclass(j)];
-          if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
-          if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
-          g[k] = a * far_j - a * own_k + own_j;
-        } else {
-          g[k] = own_j;
+          const C own_j = (C)St::to_float(own[j]) * dec[wclass(j)];
+          if constexpr (WALL == kCLI) {
+            const C a = g[k];
+            const C own_k = (C)St::to_float(own[k]) * dec[wclass(k)];
+            // g_j at the second node x_f2 = x + e_k (away from the wall) is
+            // what this node pulls in direction j, so g[j] already holds it
+            // (raw); it is read across the x-periodic plane with the pressure
+            // jump.  If x_f2 is solid, g[j] is a coefficient and a = 0.
+            C far_j = g[j] * dec[wclass(j)];
+            if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
+            if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
+            g[k] = a * far_j - a * own_k + own_j;
+          } else {
+            g[k] = own_j;
+          }
         }
       }
     }
@@ -764,6 +721,74 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
 #pragma unroll
   for (int k = 0; k < kQ; ++k) m = fmax(m, fabs(g[k]) * (C)(1.0 / kLat.w[k]));
   mom[4] = m;
+}
+
+// One time step for the node (x, y, z), fluid, with flag word fl: pull (one
+// lane, one node), the general wall rules, then finish_node.
+template <typename S, int COLL, int WALL>
+__device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[kQ],
+                                            const uint32_t* __restrict__ flags,
+                                            const StepParams& p, int x, int y, int z, int c,
+                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
+  using C = typename ComputeOf<S>::type;
+  using St = Storage<S>;
+  const int nx = p.nx, plane = p.t.plane;
+  Nbr n;
+  n.xs[0] = p.t.xpart(x == 0 ? nx - 1 : x - 1);
+  n.xs[1] = p.t.xpart(x);
+  n.xs[2] = p.t.xpart(x == nx - 1 ? 0 : x + 1);
+  n.ys[0] = p.t.ypart(y == 0 ? p.ny - 1 : y - 1);
+  n.ys[1] = p.t.ypart(y);
+  n.ys[2] = p.t.ypart(y == p.ny - 1 ? 0 : y + 1);
+  n.zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
+  n.zs[1] = z * plane;
+  n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
+
+  const long long st = p.stride;
+  C g[kQ];
+  // pull: direction k arrives from x - e_k (raw stored values)
+#pragma unroll
+  for (int k = 0; k < kQ; ++k)
+    g[k] = (C)St::to_float(src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])]);
+
+  // wall links: the pulled raw value is the stored coefficient a (CLI) or
+  // the wall distance q (general rules)
+  S own[kQ];
+  if (fl & kLinkMask) {
+    // The node's own stored values of every moving direction (the wall rules
+    // need g_j and g_k at x), all requested before the first use: one memory
+    // round trip per boundary node instead of one per link direction (512^3
+    // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
+    // come from the same values.
+#pragma unroll
+    for (int k = 1; k < kQ; ++k) own[k] = src[k * st + c];
+    if constexpr (WALL == kGEN) {
+      C m1[4] = {(C)0, (C)0, (C)0, (C)0};
+      if (p.wall == kRuleIEBB) {
+        own[0] = src[c];
+#pragma unroll
+        for (int kk = 0; kk < kQ; ++kk) {
+          const C v = (C)St::to_float(own[kk]);
+          m1[0] += v;
+          m1[1] += (C)kLat.ex[kk] * v;
+          m1[2] += (C)kLat.ey[kk] * v;
+          m1[3] += (C)kLat.ez[kk] * v;
+        }
+      }
+      // the pulled raw value is the link's wall distance q.  g[j] may already
+      // hold a wall value when direction j is a link too; the rules use the
+      // pull g[j] only when x_f2 = x - e_j is fluid, i.e. j is no link.
+#pragma unroll
+      for (int k = 1; k < kQ; ++k) {
+        if (fl & (1u << k)) {
+          const int j = kLat.opp[k];
+          g[k] = general_wall_value<S, C>(src, flags, p, x, y, z, c, k, g[k], fl, m1, g[j],
+                                          (C)St::to_float(own[j]), (C)St::to_float(own[k]));
+        }
+      }
+    }
+  }
+  finish_node<S, COLL, WALL>(g, own, out, p, x, c, fl, mom);
 }
 
 // The 19 values a solid cell writes: its wall-link slots (flag bit k: the
@@ -853,8 +878,8 @@ __device__ __forceinline__ uint32_t flag_word(uint8_t k, const uint32_t* __restr
 }
 
 // The fused stream-and-collide step over the box.  A block of blockDim.y
-// wavefronts covers that many consecutive tiles of one z plane; with 8 x 8
-// tiles and 16 wavefronts it spans 128 x 8 cells, so most of the lines that
+// wavefronts covers that many consecutive tiles of one z plane; with 16 x 4
+// tiles and 8 wavefronts it spans 128 x 4 cells, so most of the lines that
 // the +-1 shifted pulls share with neighbouring tiles are read by the same
 // workgroup.  With RED the block also writes FP64 partial sums of the state
 // it produced (u, drho, max |u|^2, non-finite count) to partials[block].  NT
@@ -898,6 +923,204 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
         v[5] = 1.0;
       v[6] = isfinite((double)mom[4]) ? (double)mom[4] : 0.0;
     }
+    const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
+    const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.z;
+    block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
+  }
+}
+
+// ------------------------------------------- two cells per lane (16-bit storage)
+// With 2-byte values a wavefront load of one value per lane moves 128 bytes,
+// and even at the full 8 wavefronts per SIMD too few bytes are in flight to
+// keep HBM busy (all-fluid 512^3 box: 0.50 of 8 TB/s against 0.64 for FP32).
+// Here each lane takes the two x-adjacent cells of one aligned 4-byte word:
+// a wavefront covers the 128 consecutive addresses of two tiles and loads 256
+// bytes per direction.  A pull with e_x = 0 reads the word at the cells' own
+// x; with e_x = +1 cell A (even x) needs the high half of the word to its
+// left, which is the next lower lane's word (a DPP row shift) except at the
+// start of a tile row or of a 16-lane DPP row, where the lane reads that word
+// itself; e_x = -1 mirrors this.  The box edge in x must fall on a tile edge
+// (nx a multiple of the tile width), so the periodic wrap only happens at the
+// reads at tile edges.  A lane whose pair holds one solid cell stores that
+// cell's own (unchanged) values with the fluid one.  Every cell goes through
+// finish_node with its own address, so the stored results are the one-cell
+// kernel's.
+
+// In-plane address of a pair wavefront's cell A and its coordinates.
+struct PairCell {
+  int a;             // in-plane address of cell A (even); cell B is a + 1
+  int x, y;          // cell A (cell B is x + 1)
+  bool inside;       // false for tiles past the plane and padding rows
+  bool edge_lo;      // the word left of the pair is not in lane - 1 of the DPP row
+  bool edge_hi;      // the word right of the pair is not in lane + 1
+};
+__device__ __forceinline__ PairCell pair_cell(const Tiling& t) {
+  const int w = blockIdx.x * blockDim.y + threadIdx.y;
+  const int l = threadIdx.x;
+  PairCell r;
+  r.a = (w << 7) + 2 * l;
+  const int tile = r.a >> 6, o = r.a & 63;
+  const int tx = tile % t.ntx, ty = tile / t.ntx;
+  const int xin = o & ((1 << t.tw_log2) - 1);
+  r.x = (tx << t.tw_log2) + xin;
+  r.y = (ty << t.th_log2) + (o >> t.tw_log2);
+  r.inside = ty < t.nty && r.y < t.ny;
+  r.edge_lo = xin == 0 || (l & 15) == 0;
+  r.edge_hi = xin == (1 << t.tw_log2) - 2 || (l & 15) == 15;
+  return r;
+}
+
+template <typename S>
+__device__ __forceinline__ S half_of(uint32_t w, int h) {
+  return __builtin_bit_cast(S, (uint16_t)(w >> (16 * h)));
+}
+template <typename S>
+__device__ __forceinline__ uint32_t bits_of(S v) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+
+template <typename S, int COLL, int WALL, bool RED, bool NT>
+__global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __restrict__ src,
+                                                                 S* __restrict__ dst,
+                                                                 const uint8_t* __restrict__ cls,
+                                                                 const uint32_t* __restrict__ flags,
+                                                                 const StepParams p,
+                                                                 double* __restrict__ partials) {
+  static_assert(sizeof(S) == 2, "two cells per lane: 16-bit storage only");
+  static_assert(WALL != kGEN, "two cells per lane: SBB and CLI only");
+  using C = typename ComputeOf<S>::type;
+  const Tiling& t = p.t;
+  const int z = blockIdx.z;
+  const PairCell pc = pair_cell(t);
+  const long long st = p.stride;
+  const int c = pc.a + z * t.plane;  // cell A
+  const uint32_t cl2 = pc.inside ? (uint32_t)(*reinterpret_cast<const uint16_t*>(cls + c))
+                                 : (uint32_t)(kClsSolid | (kClsSolid << 8));
+  const bool solid_a = cl2 & kClsSolid, solid_b = (cl2 >> 8) & kClsSolid;
+  const bool live = !(solid_a && solid_b);
+  const unsigned long long ball = __ballot(live);
+  double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (ball != 0) {
+    // the lanes of a DPP row with a fluid cell read their words (neighbours
+    // within the row need them, solid or not)
+    const bool row_reads = pc.inside && ((ball >> (threadIdx.x & 48)) & 0xffffull) != 0;
+    const int nx = p.nx, plane = t.plane;
+    const int xs_lo = t.xpart(pc.x == 0 ? nx - 2 : pc.x - 2);
+    const int xs_0 = t.xpart(pc.x);
+    const int xs_hi = t.xpart(pc.x + 2 == nx ? 0 : pc.x + 2);
+    int ys[3], zs[3];
+    ys[0] = t.ypart(pc.y == 0 ? p.ny - 1 : pc.y - 1);
+    ys[1] = t.ypart(pc.y);
+    ys[2] = t.ypart(pc.y == p.ny - 1 ? 0 : pc.y + 1);
+    zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
+    zs[1] = z * plane;
+    zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
+    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+
+    // pull: one word per direction with cell A's pulled value in the low
+    // half and cell B's in the high half (direction k from x - e_k)
+    // Every lane issues every load (no branches, so that all of them are in
+    // flight together): lanes that need no word read address 0 of the plane,
+    // and the lanes that need no edge word read their own word again.  All
+    // loads come before the first DPP shift, which waits for its word.
+    uint32_t raw[kQ], edge[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const int ex = kLat.ex[k];
+      const int row = ys[1 - kLat.ey[k]] + zs[1 - kLat.ez[k]];
+      const uint32_t* sk = s32 + ((k * st) >> 1);
+      const int a0 = row_reads ? xs_0 + row : 0;
+      raw[k] = sk[a0 >> 1];
+      if (ex == 1) edge[k] = sk[(row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
+      if (ex == -1) edge[k] = sk[(row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
+    }
+    // Boundary pairs: both flag words and the pair's own words, requested
+    // with the pulls (one memory round trip): wall rules of link cells, and
+    // the unchanged half of a pair with one solid cell (whose fluid partner
+    // then has an x link).
+    const bool links = live && (cl2 & (kClsLinks | (kClsLinks << 8))) != 0;
+    uint2 flw = make_uint2(0u, 0u);
+    uint32_t own_w[kQ];
+    if (links) {
+      flw = *reinterpret_cast<const uint2*>(flags + c);
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) own_w[k] = s32[(k * st + c) >> 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      const int ex = kLat.ex[k];
+      const uint32_t w = raw[k];
+      if (ex == 1) {
+        // A <- high half of the word on the left, B <- low half of w
+        const uint32_t prev =
+            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x111, 0xf, 0xf, true);  // row_shr:1
+        raw[k] = ((pc.edge_lo ? edge[k] : prev) >> 16) | (w << 16);
+      } else if (ex == -1) {
+        // A <- high half of w, B <- low half of the word on the right
+        const uint32_t next =
+            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x101, 0xf, 0xf, true);  // row_shl:1
+        raw[k] = (w >> 16) | ((pc.edge_hi ? edge[k] : next) << 16);
+      }
+    }
+
+    {
+      uint32_t outw[kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) outw[k] = 0;
+      // cell A (h = 0) and cell B (h = 1)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int sh = 16 * h;
+        const bool solid = h ? solid_b : solid_a;
+        const uint32_t clh = (cl2 >> (8 * h)) & 0xffu;  // class bytes: A low, B high
+        if (solid) {
+          // a solid cell beside a fluid one keeps its (constant) values
+          if (!(h ? solid_a : solid_b)) {
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) outw[k] |= (own_w[k] >> sh & 0xffffu) << sh;
+          }
+          continue;
+        }
+        const uint32_t fl = (clh & kClsLinks) ? (h ? flw.y : flw.x) : 0u;
+        S own[kQ];
+#pragma unroll
+        for (int k = 1; k < kQ; ++k) own[k] = half_of<S>(own_w[k], h);
+        C g[kQ];
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) g[k] = (C)Storage<S>::to_float(half_of<S>(raw[k], h));
+        S out[kQ];
+        C mom[5];
+        finish_node<S, COLL, WALL>(g, own, out, p, pc.x + h, c + h, fl, mom);
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) outw[k] |= bits_of<S>(out[k]) << sh;
+        if constexpr (RED) {
+          const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
+          const double u2 = ux * ux + uy * uy + uz * uz;
+          v[0] += ux;
+          v[1] += uy;
+          v[2] += uz;
+          v[3] += rho;
+          if (isfinite(u2) && isfinite(rho))
+            v[4] = fmax(v[4], u2);
+          else
+            v[5] += 1.0;
+          v[6] = fmax(v[6], isfinite((double)mom[4]) ? (double)mom[4] : 0.0);
+        }
+      }
+      if (live) {
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+          uint32_t* q = d32 + ((k * st + c) >> 1);
+          if constexpr (NT)
+            __builtin_nontemporal_store(outw[k], q);
+          else
+            *q = outw[k];
+        }
+      }
+    }
+  }
+  if constexpr (RED) {
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
     const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.z;
     block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
@@ -967,6 +1190,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     block_reduce<kRedVals>(v, kind, partials + blk * kRedVals);
   }
 }
+
+// The kernels below (checks, reductions, set-up) are compiled with the host
+// code only; the per-storage step translation units define LBM_STEP_TU and
+// stop here.
+#ifndef LBM_STEP_TU
 
 // Per-cell convergence record, updated on the device at every check.
 struct CellStatus {
@@ -1326,5 +1554,7 @@ __global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__
     }
   }
 }
+
+#endif  // LBM_STEP_TU
 
 }  // namespace lbm

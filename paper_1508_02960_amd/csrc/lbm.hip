@@ -17,6 +17,7 @@
 #include "geometry.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
+#include "step_table.hpp"
 
 #define LBM_API extern "C" __attribute__((visibility("default")))
 
@@ -32,8 +33,9 @@ struct lbm_domain_s {
   Tiling tiling{};       // tiled cell order of the device buffers
   long long naddr = 0;   // device cell addresses (cells plus tile padding)
   long long cell_addrs = 0;  // addresses per z period (one batch cell, or the box)
-  int waves = 16;        // wavefronts (tiles) per step workgroup
+  int waves = 16;        // wavefronts per step workgroup
   bool streaming = false;  // non-temporal stores in the step kernels
+  bool pairs = false;      // 16-bit storage: two cells per lane (step_pair_kernel)
   double nu = 0, omega_p = 0, omega_m = 0, s_e = 0, s_zeta = 0;
   double sigma = 1.0;    // 16-bit storage scale (h = sigma g / w), a power of two
   uint64_t step_count = 0;  // steps launched (seeds stochastic rounding)
@@ -130,16 +132,16 @@ double pick_sigma(double m) {
 // HBM channel: round the cell count up to 1024 elements, plus 512 elements.
 long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
 
-// Tiles of 64 cells.  Compact 16 x 4 tiles for states beyond the last-level
-// cache (512^3 sphere pack, FP32 CLI: 2.51 ms per step against 2.56 ms for
-// 8 x 8 tiles and 2.98 ms for rows; FP16 1.75 ms); 64 x 1 tiles (rows) for
-// smaller states, which stay largely in the 256 MB cache and where rows step
-// fastest (128^3, FP32: 54 us against 62 us for 16 x 4 tiles).
-Tiling make_tiling(int nx, int ny, bool compact) {
+// Tiles of 64 cells, 2^tw_log2 wide.  Compact tiles for states beyond the
+// last-level cache (512^3 sphere pack, FP32 CLI: 16 x 4 tiles 2.51 ms per
+// step against 2.56 ms for 8 x 8 tiles and 2.98 ms for rows); 64 x 1 tiles
+// (rows) for smaller states, which stay largely in the 256 MB cache and
+// where rows step fastest (128^3, FP32: 54 us against 62 us for 16 x 4).
+Tiling make_tiling(int nx, int ny, int tw_log2) {
   Tiling t{};
   t.nx = nx;
   t.ny = ny;
-  t.tw_log2 = compact ? 4 : 6;
+  t.tw_log2 = tw_log2;
   t.th_log2 = 6 - t.tw_log2;
   t.ntx = (nx + (1 << t.tw_log2) - 1) >> t.tw_log2;
   t.nty = (ny + (1 << t.th_log2) - 1) >> t.th_log2;
@@ -147,11 +149,15 @@ Tiling make_tiling(int nx, int ny, bool compact) {
   return t;
 }
 
-// Step workgroups: `waves` wavefronts take consecutive tiles of one z plane.
+// Step workgroups: `waves` wavefronts take consecutive tiles of one z plane
+// (one tile per wavefront, or two with two cells per lane).
+int step_units(lbm_domain d) {
+  const int tiles = d->tiling.ntx * d->tiling.nty;
+  return d->pairs ? (tiles + 1) / 2 : tiles;
+}
 dim3 step_block(lbm_domain d) { return dim3(64, d->waves, 1); }
 dim3 step_grid(lbm_domain d) {
-  const int tiles = d->tiling.ntx * d->tiling.nty;
-  return dim3((tiles + d->waves - 1) / d->waves, 1, d->geo.nz);
+  return dim3((step_units(d) + d->waves - 1) / d->waves, 1, d->geo.nz);
 }
 
 // Non-temporal stores pay once the two state buffers are well beyond the
@@ -164,16 +170,24 @@ void layout(lbm_domain d) {
   // large states: compact tiles and streaming stores (sizes estimated on the
   // unpadded cell count; padding adds at most a few percent)
   d->streaming = 2 * (size_t)kQ * (size_t)d->geo.ncell * d->elem > kStreamingBytes;
-  d->tiling = make_tiling(d->geo.nx, d->geo.ny, d->streaming);
+  // compact tiles: 16 x 4, or 32 x 2 for the two-cell lanes of the 16-bit
+  // formats (a 16-lane DPP row is then one tile row)
+  const int tw = d->streaming ? (d->elem == 2 ? 5 : 4) : 6;
+  d->tiling = make_tiling(d->geo.nx, d->geo.ny, tw);
+  // two cells per lane: 16-bit storage beyond the last-level cache (512^3
+  // sphere pack, FP16: 1.68 ms per step against 1.73 ms for one cell per
+  // lane; 128^3, in the cache: 36 us against 34 us, so not there), one
+  // domain (batches step one cell per lane), the box's x edge on a tile edge
+  d->pairs = d->elem == 2 && d->streaming && !d->batch && d->geo.nx % (1 << tw) == 0;
   d->cell_addrs = (long long)d->tiling.plane * d->geo.nz_cell;
   d->naddr = (long long)d->tiling.plane * d->geo.nz;
   const int64_t n = d->naddr;
   d->stride = plane_stride(n);
-  // 8 wavefronts (128 x 4 cells) with compact tiles, 4 (256 cells of a row)
-  // with rows; never more than a plane has tiles
-  const int tiles = d->tiling.ntx * d->tiling.nty;
-  d->waves = d->streaming ? 8 : 4;
-  while (d->waves > 1 && d->waves / 2 >= tiles) d->waves /= 2;
+  // 8 wavefronts (16 x 4 tiles: 128 x 4 cells) with compact tiles, 2 with
+  // two cells per lane (32 x 8 cells), 4 (256 cells of a row) with rows;
+  // never more than a plane has work for
+  d->waves = d->streaming ? (d->pairs ? 2 : 8) : 4;
+  while (d->waves > 1 && d->waves / 2 >= step_units(d)) d->waves /= 2;
   static_assert(16 * 64 <= kStepThreads, "step workgroups exceed the kernel's launch bound");
   size_t o = 0;
   const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
@@ -190,8 +204,12 @@ void layout(lbm_domain d) {
   o += align256(std::max<size_t>(nl, 1) * 8);
   d->off_coef = o;
   o += align256(std::max<size_t>(nl, 1) * 8);
+  // partial sums: room for every step shape of lbm_set_step_shape with at
+  // least two wavefronts per workgroup (at most tiles / 2 blocks per plane)
   const dim3 sg = step_grid(d);
+  const long long tiles = (long long)d->tiling.ntx * d->tiling.nty;
   d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
+  d->n_partials = std::max<long long>(d->n_partials, (tiles + 1) / 2 * d->geo.nz);
   if (d->batch) {
     // most blocks: one tile and one z plane per block
     d->n_partials = std::max<long long>(
@@ -251,41 +269,11 @@ StepParams step_params(lbm_domain d) {
 // interpolated rules share the general one (FP32/FP64 storage only).
 int wall_template(int wall) { return wall <= LBM_WALL_CLI ? wall : kGEN; }
 
-template <typename S>
-constexpr bool kUnscaled = std::is_same_v<S, float> || std::is_same_v<S, double>;
-
-template <typename S, bool RED, bool NT>
-const void* step_fn(int collision, int wall) {
-  if constexpr (kUnscaled<S>) {
-    if (wall_template(wall) == kGEN) {
-      switch (collision) {
-        case 0: return (const void*)step_kernel<S, kSRT, kGEN, RED, NT>;
-        case 1: return (const void*)step_kernel<S, kTRT, kGEN, RED, NT>;
-        default: return (const void*)step_kernel<S, kMRT, kGEN, RED, NT>;
-      }
-    }
-  }
-  switch (collision * 2 + wall_template(wall)) {
-    case 0: return (const void*)step_kernel<S, kSRT, kSBB, RED, NT>;
-    case 1: return (const void*)step_kernel<S, kSRT, kCLI, RED, NT>;
-    case 2: return (const void*)step_kernel<S, kTRT, kSBB, RED, NT>;
-    case 3: return (const void*)step_kernel<S, kTRT, kCLI, RED, NT>;
-    case 4: return (const void*)step_kernel<S, kMRT, kSBB, RED, NT>;
-    default: return (const void*)step_kernel<S, kMRT, kCLI, RED, NT>;
-  }
-}
-
-template <typename S, bool RED>
-const void* step_fn_store(bool streaming, int collision, int wall) {
-  if (streaming) return step_fn<S, RED, true>(collision, wall);
-  return step_fn<S, RED, false>(collision, wall);
-}
-
 const void* step_function(lbm_domain d, bool red) {
   return with_storage(d->p.storage, [&](auto tag) -> const void* {
     using S = decltype(tag);
-    return red ? step_fn_store<S, true>(d->streaming, d->p.collision, d->p.wall)
-               : step_fn_store<S, false>(d->streaming, d->p.collision, d->p.wall);
+    return step_kernel_entry<S>(red, d->streaming, d->pairs, d->p.collision,
+                                wall_template(d->p.wall));
   });
 }
 
@@ -386,36 +374,11 @@ dim3 batch_grid(lbm_domain d) {
               (unsigned)((long long)d->batch * d->geo.nz_cell / d->zper));
 }
 
-template <typename S, bool RED, bool NT>
-const void* batch_fn(int collision, int wall) {
-  if (wall_template(wall) == kGEN) {
-    switch (collision) {
-      case 0: return (const void*)batch_step_kernel<S, kSRT, kGEN, RED, NT>;
-      case 1: return (const void*)batch_step_kernel<S, kTRT, kGEN, RED, NT>;
-      default: return (const void*)batch_step_kernel<S, kMRT, kGEN, RED, NT>;
-    }
-  }
-  switch (collision * 2 + wall) {
-    case 0: return (const void*)batch_step_kernel<S, kSRT, kSBB, RED, NT>;
-    case 1: return (const void*)batch_step_kernel<S, kSRT, kCLI, RED, NT>;
-    case 2: return (const void*)batch_step_kernel<S, kTRT, kSBB, RED, NT>;
-    case 3: return (const void*)batch_step_kernel<S, kTRT, kCLI, RED, NT>;
-    case 4: return (const void*)batch_step_kernel<S, kMRT, kSBB, RED, NT>;
-    default: return (const void*)batch_step_kernel<S, kMRT, kCLI, RED, NT>;
-  }
-}
-
-template <typename S>
-const void* batch_fn_store(bool red, bool streaming, int collision, int wall) {
-  if (streaming)
-    return red ? batch_fn<S, true, true>(collision, wall) : batch_fn<S, false, true>(collision, wall);
-  return red ? batch_fn<S, true, false>(collision, wall) : batch_fn<S, false, false>(collision, wall);
-}
-
 const void* batch_function(lbm_domain d, bool red) {
+  const int wt = wall_template(d->p.wall);
   if (d->p.storage == LBM_FP64)
-    return batch_fn_store<double>(red, d->streaming, d->p.collision, d->p.wall);
-  return batch_fn_store<float>(red, d->streaming, d->p.collision, d->p.wall);
+    return batch_kernel_entry<double>(red, d->streaming, d->p.collision, wt);
+  return batch_kernel_entry<float>(red, d->streaming, d->p.collision, wt);
 }
 
 // Kernel-node or launch arguments of one batch step from buffer `from`.
@@ -836,6 +799,8 @@ LBM_API lbm_status lbm_get_info(lbm_domain d, lbm_info* info) {
   info->omega_minus = d->omega_m;
   info->bytes_per_fluid_update = (int64_t)(2 * kQ * d->elem);
   info->storage_scale = d->sigma;
+  info->tile_width = 1 << d->tiling.tw_log2;
+  info->tile_height = 1 << d->tiling.th_log2;
   return LBM_OK;
 }
 
@@ -1299,7 +1264,7 @@ LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   const bool gen = wall_template(d->p.wall) == kGEN;
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
-    if constexpr (kUnscaled<S>) {
+    if constexpr (kUnscaledStorage<S>) {
       if (gen) {
         drag_kernel<S, kGEN><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
             (const S*)d->buf[d->cur], d->flags, sp, d->partials);
@@ -1435,6 +1400,36 @@ LBM_API lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64
     if (residual) residual[b] = c.res;
     if (status) status[b] = c.status;
   }
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t pairs) {
+  if (!d || d->batch) return LBM_ERR_INVALID_ARG;
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
+    return fail(d, LBM_ERR_INVALID_ARG, "waves must be 1, 2, 4, 8 or 16");
+  if (pairs != 0 && pairs != 1) return fail(d, LBM_ERR_INVALID_ARG, "pairs must be 0 or 1");
+  if (pairs && (d->elem != 2 || d->geo.nx % (1 << d->tiling.tw_log2) != 0))
+    return fail(d, LBM_ERR_INVALID_ARG,
+                "two cells per lane need 16-bit storage and nx a multiple of the tile width " +
+                    std::to_string(1 << d->tiling.tw_log2));
+  const int old_waves = d->waves;
+  const bool old_pairs = d->pairs;
+  d->waves = waves;
+  d->pairs = pairs != 0;
+  const dim3 g = step_grid(d);
+  if ((long long)g.x * g.y * g.z > d->n_partials) {
+    d->waves = old_waves;
+    d->pairs = old_pairs;
+    return fail(d, LBM_ERR_INVALID_ARG, "shape needs more partial sums than the workspace holds");
+  }
+  drop_graphs(d);
+  return LBM_OK;
+}
+
+LBM_API lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* pairs) {
+  if (!d || d->batch) return LBM_ERR_INVALID_ARG;
+  if (waves) *waves = d->waves;
+  if (pairs) *pairs = d->pairs ? 1 : 0;
   return LBM_OK;
 }
 

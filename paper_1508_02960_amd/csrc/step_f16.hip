@@ -1,0 +1,10 @@
+// Step kernels for FP16 storage (stochastic and round-to-nearest rounding),
+// instantiated here for the entry points of step_table.hpp.
+#include <hip/hip_runtime.h>
+
+#include "step_impl.hpp"
+
+namespace lbm {
+template const void* step_kernel_entry<fp16s_t>(bool, bool, bool, int, int);
+template const void* step_kernel_entry<fp16_t>(bool, bool, bool, int, int);
+}  // namespace lbm

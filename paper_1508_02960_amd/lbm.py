@@ -29,7 +29,7 @@ EXPORTS = (
     "lbm_last_error", "lbm_create_batch", "lbm_batch_results", "lbm_batch_set_shape",
     "lbm_batch_autotune", "lbm_macroscopic_device", "lbm_init_equilibrium_device",
     "lbm_set_solid_writes", "lbm_get_solid_writes", "lbm_bandwidth_probe",
-    "lbm_mean_velocity_static",
+    "lbm_mean_velocity_static", "lbm_set_step_shape", "lbm_get_step_shape",
 )
 
 PROBES = {"read": 0, "write": 1, "copy": 2, "gather19": 3}
@@ -69,7 +69,8 @@ class Info(C.Structure):
                 ("n_fallback", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("plane_stride", C.c_int64), ("nu", C.c_double), ("omega_plus", C.c_double),
                 ("omega_minus", C.c_double), ("bytes_per_fluid_update", C.c_int64),
-                ("storage_scale", C.c_double)]
+                ("storage_scale", C.c_double), ("tile_width", C.c_int32),
+                ("tile_height", C.c_int32)]
 
 
 _lib = None
@@ -112,6 +113,8 @@ def library():
         "lbm_create_batch": [i32, vp, vp, vp, vp, P(Params), P(vp)],
         "lbm_batch_results": [vp, vp, vp, vp, vp, vp],
         "lbm_batch_set_shape": [vp, i32, i32],
+        "lbm_set_step_shape": [vp, i32, i32],
+        "lbm_get_step_shape": [vp, P(i32), P(i32)],
         "lbm_batch_autotune": [vp, i32, P(i32), P(i32), P(d)],
         "lbm_set_solid_writes": [vp, i32],
         "lbm_get_solid_writes": [vp, P(i32)],
@@ -288,6 +291,15 @@ class Domain:
         if status is None or (raise_on_fail and st != 0):
             self._check(st)
         return status, done.value, res.value
+
+    def step_shape(self):
+        """(wavefronts per workgroup, two cells per lane) of the step launch."""
+        w, pr = C.c_int32(), C.c_int32()
+        self._check(library().lbm_get_step_shape(self._h, C.byref(w), C.byref(pr)))
+        return w.value, bool(pr.value)
+
+    def set_step_shape(self, waves: int, pairs: bool) -> None:
+        self._check(library().lbm_set_step_shape(self._h, int(waves), int(bool(pairs))))
 
     def set_delta_rho(self, delta_rho: float) -> None:
         self._check(library().lbm_set_delta_rho(self._h, float(delta_rho)))

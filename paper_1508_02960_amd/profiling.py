@@ -19,19 +19,25 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hpp")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "step_impl.hpp")]
 
 
 def kernel_source_hash() -> str:
     """sha256[:16] of the step kernels' source with comments and blank space
-    removed, so that counters stay attached to the code they measured."""
+    removed, and of the compiler flags, so that counters stay attached to the
+    code they measured."""
     import re
 
-    src = open(KERNEL_SOURCE).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    src = re.sub(r"//[^\n]*", "", src)
-    src = "\n".join(line.strip() for line in src.splitlines() if line.strip())
-    return hashlib.sha256(src.encode()).hexdigest()[:16]
+    from .build import HIPCC_FLAGS
+
+    parts = []
+    for path in KERNEL_SOURCES:
+        src = open(path).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        parts.append("\n".join(line.strip() for line in src.splitlines() if line.strip()))
+    parts.append(" ".join(HIPCC_FLAGS))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
 def short_name(full: str) -> str:

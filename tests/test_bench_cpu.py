@@ -19,17 +19,19 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_traffic_is_reported_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     """The bench quotes HBM traffic from a committed counter record only while
-    that record was taken on the current step-kernel source and workload; any
-    change to the kernels turns the figure into null until counters are taken
-    again."""
-    wl = bench.DEFAULT_WORKLOAD
+    that record was taken on the current step-kernel source, compiler flags,
+    kernel and workload; any change to the kernels turns the figure into null
+    until counters are taken again."""
+    wl, k = bench.DEFAULT_WORKLOAD, "step_kernel"
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
-    assert bench.stored_traffic(wl, 0) is None  # no record
-    rec = {"workload": wl, "kernel_source_sha256_16": bench.kernel_source_hash(),
+    assert bench.stored_traffic(k, wl) is None  # no record
+    rec = {"workload": wl, "kernel": k, "kernel_source_sha256_16": bench.kernel_source_hash(),
            "hbm_bytes_per_launch": 123456789}
-    (tmp_path / f"step_kernel_{wl}_traffic.json").write_text(json.dumps(rec))
-    assert bench.stored_traffic(wl, 0) == 123456789
+    path = tmp_path / f"{k}_{wl}_traffic.json"
+    path.write_text(json.dumps(rec))
+    assert bench.stored_traffic(k, wl) == 123456789
+    assert bench.stored_traffic("step_pair_kernel", wl) is None  # another kernel
     rec["kernel_source_sha256_16"] = "0" * 16
-    (tmp_path / f"step_kernel_{wl}_traffic.json").write_text(json.dumps(rec))
-    assert bench.stored_traffic(wl, 0) is None
-    assert bench.stored_traffic("no_such_workload", 0) is None
+    path.write_text(json.dumps(rec))
+    assert bench.stored_traffic(k, wl) is None
+    assert bench.stored_traffic(k, "no_such_workload") is None

@@ -685,6 +685,26 @@ def test_permeability_independent_of_viscosity_trt(orc):
 
 
 @pytest.mark.slow
+def test_permeability_viscosity_dependence_by_operator(orc):
+    """Sec. 3.2 (viscosity study, nu from 0.033 to 0.3): the Stokes
+    permeability of a sphere cell moves strongly with viscosity under SRT,
+    much less under MRT (Pan's s_zeta on the kinetic modes, energy modes at a
+    fixed ratio), not at all under TRT with CLI or MR, and LIBB stays
+    viscosity-dependent even with TRT."""
+    def spread(collision, wall):
+        Ks = [_sphere_cell_K(orc, 10, 6.0, tau, collision=collision, wall=wall)[1]
+              for tau in (0.6, 1.4)]
+        return abs(Ks[1] / Ks[0] - 1)
+
+    srt, mrt = spread("srt", "cli"), spread("mrt", "cli")
+    assert srt > 0.1, srt
+    assert mrt < 0.25 * srt, (mrt, srt)
+    assert spread("trt", "cli") < 1e-6
+    assert spread("trt", "mr") < 1e-6
+    assert spread("trt", "libb") > 1e-3
+
+
+@pytest.mark.slow
 def test_drag_against_simple_cubic_series(orc):
     """eq. (AnalyticForce) against the semi-analytic drag of a simple-cubic
     array at solid volume fraction c (Sec. 3.1, d/L = 0.6).  The series
