@@ -265,7 +265,7 @@ def main() -> int:
     n_fluid, n_cells = d.n_fluid, d.ncell
     stream = d.stream
     # the step kernel this shape launches (two cells per lane for large 16-bit states)
-    kernel = "step_pair_kernel" if d.step_shape()[1] else "step_kernel"
+    kernel = "step_pair_kernel" if d.step_shape()[2] else "step_kernel"
     print(f"[bench] workload {args.workload}: {n_cells} cells, {n_fluid} fluid, "
           f"{d.info.n_links} links, workspace {d.info.workspace_bytes / 2**30:.2f} GiB",
           file=sys.stderr, flush=True)

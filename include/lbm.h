@@ -184,15 +184,18 @@ lbm_status lbm_get_state(lbm_domain d, double* g);
 lbm_status lbm_step(lbm_domain d, int64_t n);
 
 /* Launch shape of the single-domain step: wavefronts per workgroup (waves:
- * 1, 2, 4, 8 or 16) and whether 16-bit storage steps two x-adjacent cells
- * per lane (pairs 1) or one (pairs 0).  Results do not depend on the shape
- * (the stored state is the same bit for bit); only the speed does.  The
- * library picks a shape at lbm_bind; this call overrides it (for tuning and
+ * 1, 2, 4, 8 or 16), arranged as waves / rows wavefronts across times `rows`
+ * tile rows (rows divides waves), and whether 16-bit storage steps two
+ * x-adjacent cells per lane (pairs 1: a wavefront takes two tiles of a tile
+ * row) or one (pairs 0: one tile).  Results do not depend on the shape (the
+ * stored state is the same bit for bit); only the speed does.  The library
+ * picks a shape at lbm_create_domain; this call overrides it (for tuning and
  * tests).  pairs 1 needs FP16/BF16 storage and nx a multiple of the tile
- * width that lbm_get_info reports.  LBM_ERR_INVALID_ARG otherwise, or for a
- * batch. */
-lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t pairs);
-lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* pairs);
+ * width that lbm_get_info reports.  LBM_ERR_INVALID_ARG otherwise, for a
+ * shape with more workgroups than the workspace has partial sums for, or for
+ * a batch. */
+lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t rows, int32_t pairs);
+lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* rows, int32_t* pairs);
 
 /* Step until the relative change of the superficial mean velocity U_x over
  * check_interval steps stays below tol for three checks in a row (stopping

@@ -92,6 +92,10 @@ struct StepParams {
   unsigned seed;      // stochastic rounding: per-step seed
   int wall;           // wall rule (lbm_wall) for the general wall template
   int solid_writes;   // batches: which solid cells store (solid_stores): 0, 1, 2
+  // single-domain step workgroups: bw x bh wavefronts cover bw units (a tile,
+  // or two x-adjacent tiles with two cells per lane) of bh consecutive tile
+  // rows; nbx workgroups span a band of bh tile rows
+  int bw, bh, nbx;
 };
 
 // ------------------------------------------------------------ storage types
@@ -870,6 +874,30 @@ __device__ __forceinline__ TileCell tile_cell(const Tiling& t, int z) {
   return r;
 }
 
+// Unit column and tile row of this wavefront in a step workgroup (the bw x
+// bh arrangement of StepParams; workgroups run along a band of tile rows,
+// then the next band).  Units past the row end give u >= units per row.
+__device__ __forceinline__ void step_unit(const StepParams& p, int& u, int& ty) {
+  const int j = threadIdx.y;
+  const int bx = blockIdx.x % p.nbx, by = blockIdx.x / p.nbx;
+  u = bx * p.bw + j % p.bw;
+  ty = by * p.bh + j / p.bw;
+}
+
+// tile_cell for the single-domain step: the tile is the wavefront's unit.
+__device__ __forceinline__ TileCell step_tile_cell(const StepParams& p, int z) {
+  const Tiling& t = p.t;
+  int tx, ty;
+  step_unit(p, tx, ty);
+  const int l = threadIdx.x;
+  TileCell r;
+  r.x = (tx << t.tw_log2) + (l & ((1 << t.tw_log2) - 1));
+  r.y = (ty << t.th_log2) + (l >> t.tw_log2);
+  r.inside = tx < t.ntx && ty < t.nty && r.x < t.nx && r.y < t.ny;
+  r.c = ((ty * t.ntx + tx) << 6) + l + z * t.plane;
+  return r;
+}
+
 // Flag word of a cell from its class byte: only cells with wall links (or
 // link slots, for solid cells) read the word.
 __device__ __forceinline__ uint32_t flag_word(uint8_t k, const uint32_t* __restrict__ flags, int c) {
@@ -893,7 +921,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
                                                             double* __restrict__ partials) {
   using C = typename ComputeOf<S>::type;
   const int z = blockIdx.z;
-  const TileCell tc = tile_cell(p.t, z);
+  const TileCell tc = step_tile_cell(p, z);
   const long long st = p.stride;
   const uint8_t k = tc.inside ? cls[tc.c] : kClsSolid;
   if constexpr (!RED) {
@@ -946,25 +974,29 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
 // finish_node with its own address, so the stored results are the one-cell
 // kernel's.
 
-// In-plane address of a pair wavefront's cell A and its coordinates.
+// In-plane address of a pair wavefront's cell A and its coordinates.  The
+// wavefront's unit u is the tiles 2u and 2u + 1 of its tile row (lanes 0-31
+// and 32-63), 128 consecutive addresses when both exist.
 struct PairCell {
   int a;             // in-plane address of cell A (even); cell B is a + 1
   int x, y;          // cell A (cell B is x + 1)
-  bool inside;       // false for tiles past the plane and padding rows
+  bool inside;       // false for tiles past the row or plane and padding rows
   bool edge_lo;      // the word left of the pair is not in lane - 1 of the DPP row
   bool edge_hi;      // the word right of the pair is not in lane + 1
 };
-__device__ __forceinline__ PairCell pair_cell(const Tiling& t) {
-  const int w = blockIdx.x * blockDim.y + threadIdx.y;
+__device__ __forceinline__ PairCell pair_cell(const StepParams& p) {
+  const Tiling& t = p.t;
+  int u, ty;
+  step_unit(p, u, ty);
   const int l = threadIdx.x;
-  PairCell r;
-  r.a = (w << 7) + 2 * l;
-  const int tile = r.a >> 6, o = r.a & 63;
-  const int tx = tile % t.ntx, ty = tile / t.ntx;
+  const int tx = 2 * u + (l >> 5);
+  const int o = (2 * l) & 63;
   const int xin = o & ((1 << t.tw_log2) - 1);
+  PairCell r;
+  r.a = ((ty * t.ntx + tx) << 6) + o;
   r.x = (tx << t.tw_log2) + xin;
   r.y = (ty << t.th_log2) + (o >> t.tw_log2);
-  r.inside = ty < t.nty && r.y < t.ny;
+  r.inside = tx < t.ntx && ty < t.nty && r.y < t.ny;
   r.edge_lo = xin == 0 || (l & 15) == 0;
   r.edge_hi = xin == (1 << t.tw_log2) - 2 || (l & 15) == 15;
   return r;
@@ -991,7 +1023,7 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
   using C = typename ComputeOf<S>::type;
   const Tiling& t = p.t;
   const int z = blockIdx.z;
-  const PairCell pc = pair_cell(t);
+  const PairCell pc = pair_cell(p);
   const long long st = p.stride;
   const int c = pc.a + z * t.plane;  // cell A
   const uint32_t cl2 = pc.inside ? (uint32_t)(*reinterpret_cast<const uint16_t*>(cls + c))

@@ -34,6 +34,7 @@ struct lbm_domain_s {
   long long naddr = 0;   // device cell addresses (cells plus tile padding)
   long long cell_addrs = 0;  // addresses per z period (one batch cell, or the box)
   int waves = 16;        // wavefronts per step workgroup
+  int rows = 1;          // tile rows per step workgroup (waves / rows units across)
   bool streaming = false;  // non-temporal stores in the step kernels
   bool pairs = false;      // 16-bit storage: two cells per lane (step_pair_kernel)
   double nu = 0, omega_p = 0, omega_m = 0, s_e = 0, s_zeta = 0;
@@ -149,15 +150,20 @@ Tiling make_tiling(int nx, int ny, int tw_log2) {
   return t;
 }
 
-// Step workgroups: `waves` wavefronts take consecutive tiles of one z plane
-// (one tile per wavefront, or two with two cells per lane).
-int step_units(lbm_domain d) {
-  const int tiles = d->tiling.ntx * d->tiling.nty;
-  return d->pairs ? (tiles + 1) / 2 : tiles;
+// Step workgroups: waves / rows wavefronts across times `rows` tile rows of
+// one z plane; a wavefront takes a unit of a tile row (one tile, or two
+// x-adjacent tiles with two cells per lane).
+int step_units_per_row(lbm_domain d) {
+  return d->pairs ? (d->tiling.ntx + 1) / 2 : d->tiling.ntx;
+}
+int step_nbx(lbm_domain d) {
+  const int bw = d->waves / d->rows;
+  return (step_units_per_row(d) + bw - 1) / bw;
 }
 dim3 step_block(lbm_domain d) { return dim3(64, d->waves, 1); }
 dim3 step_grid(lbm_domain d) {
-  return dim3((step_units(d) + d->waves - 1) / d->waves, 1, d->geo.nz);
+  const int nby = (d->tiling.nty + d->rows - 1) / d->rows;
+  return dim3(step_nbx(d) * nby, 1, d->geo.nz);
 }
 
 // Non-temporal stores pay once the two state buffers are well beyond the
@@ -187,7 +193,10 @@ void layout(lbm_domain d) {
   // two cells per lane (32 x 8 cells), 4 (256 cells of a row) with rows;
   // never more than a plane has work for
   d->waves = d->streaming ? (d->pairs ? 2 : 8) : 4;
-  while (d->waves > 1 && d->waves / 2 >= step_units(d)) d->waves /= 2;
+  const int units = step_units_per_row(d);
+  d->rows = 1;
+  while (d->waves / d->rows > units && d->rows < d->tiling.nty) d->rows *= 2;
+  while (d->waves > d->rows && d->waves / d->rows > units) d->waves /= 2;
   static_assert(16 * 64 <= kStepThreads, "step workgroups exceed the kernel's launch bound");
   size_t o = 0;
   const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
@@ -204,12 +213,13 @@ void layout(lbm_domain d) {
   o += align256(std::max<size_t>(nl, 1) * 8);
   d->off_coef = o;
   o += align256(std::max<size_t>(nl, 1) * 8);
-  // partial sums: room for every step shape of lbm_set_step_shape with at
-  // least two wavefronts per workgroup (at most tiles / 2 blocks per plane)
+  // partial sums: room for the step shapes of lbm_set_step_shape with at
+  // least two wavefronts per workgroup (about tiles / 2 blocks per plane)
   const dim3 sg = step_grid(d);
-  const long long tiles = (long long)d->tiling.ntx * d->tiling.nty;
+  const long long half_row = (d->tiling.ntx + 1) / 2;
   d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
-  d->n_partials = std::max<long long>(d->n_partials, (tiles + 1) / 2 * d->geo.nz);
+  d->n_partials =
+      std::max<long long>(d->n_partials, half_row * d->tiling.nty * (long long)d->geo.nz);
   if (d->batch) {
     // most blocks: one tile and one z plane per block
     d->n_partials = std::max<long long>(
@@ -261,6 +271,9 @@ StepParams step_params(lbm_domain d) {
   sp.sigma = d->sigma;
   sp.wall = d->p.wall;
   sp.solid_writes = d->solid_writes;
+  sp.bw = std::max(1, d->waves / std::max(1, d->rows));
+  sp.bh = std::max(1, d->rows);
+  sp.nbx = d->batch ? 1 : step_nbx(d);
   sp.seed = hash32((uint32_t)d->step_count ^ hash32((uint32_t)(d->step_count >> 32) + 0x5bd1e995u));
   return sp;
 }
@@ -1403,22 +1416,27 @@ LBM_API lbm_status lbm_batch_results(lbm_domain d, double* U, double* K_D, int64
   return LBM_OK;
 }
 
-LBM_API lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t pairs) {
+LBM_API lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t rows,
+                                      int32_t pairs) {
   if (!d || d->batch) return LBM_ERR_INVALID_ARG;
   if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
     return fail(d, LBM_ERR_INVALID_ARG, "waves must be 1, 2, 4, 8 or 16");
+  if (rows < 1 || waves % rows != 0)
+    return fail(d, LBM_ERR_INVALID_ARG, "rows must divide waves");
   if (pairs != 0 && pairs != 1) return fail(d, LBM_ERR_INVALID_ARG, "pairs must be 0 or 1");
   if (pairs && (d->elem != 2 || d->geo.nx % (1 << d->tiling.tw_log2) != 0))
     return fail(d, LBM_ERR_INVALID_ARG,
                 "two cells per lane need 16-bit storage and nx a multiple of the tile width " +
                     std::to_string(1 << d->tiling.tw_log2));
-  const int old_waves = d->waves;
+  const int old_waves = d->waves, old_rows = d->rows;
   const bool old_pairs = d->pairs;
   d->waves = waves;
+  d->rows = rows;
   d->pairs = pairs != 0;
   const dim3 g = step_grid(d);
   if ((long long)g.x * g.y * g.z > d->n_partials) {
     d->waves = old_waves;
+    d->rows = old_rows;
     d->pairs = old_pairs;
     return fail(d, LBM_ERR_INVALID_ARG, "shape needs more partial sums than the workspace holds");
   }
@@ -1426,9 +1444,11 @@ LBM_API lbm_status lbm_set_step_shape(lbm_domain d, int32_t waves, int32_t pairs
   return LBM_OK;
 }
 
-LBM_API lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* pairs) {
+LBM_API lbm_status lbm_get_step_shape(lbm_domain d, int32_t* waves, int32_t* rows,
+                                      int32_t* pairs) {
   if (!d || d->batch) return LBM_ERR_INVALID_ARG;
   if (waves) *waves = d->waves;
+  if (rows) *rows = d->rows;
   if (pairs) *pairs = d->pairs ? 1 : 0;
   return LBM_OK;
 }

@@ -113,8 +113,8 @@ def library():
         "lbm_create_batch": [i32, vp, vp, vp, vp, P(Params), P(vp)],
         "lbm_batch_results": [vp, vp, vp, vp, vp, vp],
         "lbm_batch_set_shape": [vp, i32, i32],
-        "lbm_set_step_shape": [vp, i32, i32],
-        "lbm_get_step_shape": [vp, P(i32), P(i32)],
+        "lbm_set_step_shape": [vp, i32, i32, i32],
+        "lbm_get_step_shape": [vp, P(i32), P(i32), P(i32)],
         "lbm_batch_autotune": [vp, i32, P(i32), P(i32), P(d)],
         "lbm_set_solid_writes": [vp, i32],
         "lbm_get_solid_writes": [vp, P(i32)],
@@ -293,13 +293,15 @@ class Domain:
         return status, done.value, res.value
 
     def step_shape(self):
-        """(wavefronts per workgroup, two cells per lane) of the step launch."""
-        w, pr = C.c_int32(), C.c_int32()
-        self._check(library().lbm_get_step_shape(self._h, C.byref(w), C.byref(pr)))
-        return w.value, bool(pr.value)
+        """(wavefronts per workgroup, tile rows per workgroup, two cells per
+        lane) of the step launch."""
+        w, r, pr = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(library().lbm_get_step_shape(self._h, C.byref(w), C.byref(r), C.byref(pr)))
+        return w.value, r.value, bool(pr.value)
 
-    def set_step_shape(self, waves: int, pairs: bool) -> None:
-        self._check(library().lbm_set_step_shape(self._h, int(waves), int(bool(pairs))))
+    def set_step_shape(self, waves: int, rows: int, pairs: bool) -> None:
+        self._check(library().lbm_set_step_shape(self._h, int(waves), int(rows),
+                                                 int(bool(pairs))))
 
     def set_delta_rho(self, delta_rho: float) -> None:
         self._check(library().lbm_set_delta_rho(self._h, float(delta_rho)))

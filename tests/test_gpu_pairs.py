@@ -35,11 +35,11 @@ def _pair_and_single(shape, storage, steps, *, residual_run=False, large=False, 
         g0 = inputs.random_populations(shape, 1e-3, seed=5)
     for pairs in (True, False):
         d = lbm.Domain(shape, storage=storage, **kw)
-        waves, default_pairs = d.step_shape()
+        waves, rows, default_pairs = d.step_shape()
         # states beyond 1 GiB pair cells by default, smaller ones do not
         assert default_pairs == large
-        d.set_step_shape(waves, pairs)
-        assert d.step_shape() == (waves, pairs)
+        d.set_step_shape(waves, rows, pairs)
+        assert d.step_shape() == (waves, rows, pairs)
         if large:
             d.init_equilibrium(drho0, u0)
         else:
@@ -97,19 +97,21 @@ def test_pair_kernel_large_state_tiles():
 def test_pair_shape_rejected_where_it_cannot_run():
     shape = (4, 6, 70)  # nx not a multiple of the 64-cell rows
     d = lbm.Domain(shape, tau=0.8, storage="fp16", mask=np.zeros(shape, np.uint8))
-    assert d.step_shape() == (4, False)
+    assert d.step_shape()[2] is False
     with pytest.raises(lbm.LbmError):
-        d.set_step_shape(4, True)
+        d.set_step_shape(4, 4, True)
     d.close()
     d = lbm.Domain((4, 6, 64), tau=0.8, storage="fp16", mask=np.zeros((4, 6, 64), np.uint8))
-    d.set_step_shape(2, True)
-    assert d.step_shape() == (2, True)
+    d.set_step_shape(2, 2, True)
+    assert d.step_shape() == (2, 2, True)
     d.close()
     d = lbm.Domain((4, 6, 64), tau=0.8, storage="fp32", mask=np.zeros((4, 6, 64), np.uint8))
     with pytest.raises(lbm.LbmError):
-        d.set_step_shape(4, True)
+        d.set_step_shape(4, 4, True)  # pairs need 16-bit storage
     with pytest.raises(lbm.LbmError):
-        d.set_step_shape(3, False)
+        d.set_step_shape(3, 1, False)  # waves not a power of two
+    with pytest.raises(lbm.LbmError):
+        d.set_step_shape(4, 3, False)  # rows must divide waves
     d.close()
 
 
@@ -123,7 +125,7 @@ def test_pair_kernel_matches_oracle(orc, storage):
     sp = inputs.random_spheres(shape, 6, (1.5, 4.0), seed=21)
     kw = dict(tau=0.7, magic=0.21, delta_rho=3e-3, collision="trt", wall="cli", spheres=sp)
     d = lbm.Domain(shape, storage=storage, **kw)
-    d.set_step_shape(4, True)
+    d.set_step_shape(4, 4, True)
     d.set_state(inputs.random_populations(shape, 1e-3, seed=22))
     g_held = d.get_state()
     o = orc.Oracle(shape, **kw)
