@@ -112,9 +112,10 @@ def test_low_viscosity_blow_up_step_matches_oracle(orc):
     """The turbulent workload scaled down to a 32^3 cell (sphere D = 30,
     tau = 0.5005, pressure drop of the Re_p = 5812 target, 1% seeded random
     start velocity) is under-resolved and blows up.  TRT (Lambda = 6e-6) and
-    MRT become unstable (non-finite or |u| > c_s) at the same check step on
-    the GPU (FP64) as in the oracle, so the blow-up belongs to the scheme at
-    this resolution, not to the kernels."""
+    MRT with CLI walls, and TRT with QIBB walls (within a few hundred steps),
+    become unstable (non-finite or |u| > c_s) at the same check step on the
+    GPU (FP64) as in the oracle, so the blow-up belongs to the scheme at this
+    resolution, not to the kernels."""
     import os
 
     edge = 32
@@ -127,8 +128,8 @@ def test_low_viscosity_blow_up_step_matches_oracle(orc):
     u0 = 0.01 * U * inputs.random_velocity(shape, 1.0, seed=3)
     orc.set_threads(min(16, os.cpu_count() or 1))
     try:
-        for coll in ("mrt", "trt"):
-            kw = dict(tau=0.5005, magic=6e-6, delta_rho=drho, collision=coll, wall="cli",
+        for coll, wall in (("mrt", "cli"), ("trt", "cli"), ("trt", "qibb")):
+            kw = dict(tau=0.5005, magic=6e-6, delta_rho=drho, collision=coll, wall=wall,
                       spheres=inputs.centred_sphere(shape, D))
             o = orc.Oracle(shape, **kw)
             o.init(u0=u0)
@@ -137,8 +138,8 @@ def test_low_viscosity_blow_up_step_matches_oracle(orc):
             d.init_equilibrium(u0=u0)
             sd, nd, _ = d.run_to_residual(0.0, 6000)
             d.close()
-            assert so == sd == "unstable", (coll, so, sd)
-            assert nd == no, (coll, nd, no)
+            assert so == sd == "unstable", (coll, wall, so, sd)
+            assert nd == no, (coll, wall, nd, no)
     finally:
         orc.set_threads(1)
 
