@@ -36,6 +36,12 @@ extern "C" {
 lbm_status nn_conv3d_forward(const void* x, const void* w, const float* bias, float* y, int n,
                              int d, int h, int w_, int ci, int co, void* stream);
 
+/* The forward convolution followed by nn_activation_forward, in one kernel:
+ * a = bf16(relu ? max(y, 0) : y) (bf16, n,d,h,w,co; relu 0 or 1) with y as
+ * above, never stored in FP32.  Bit-identical to the two calls. */
+lbm_status nn_conv3d_forward_act(const void* x, const void* w, const float* bias, void* a, int n,
+                                 int d, int h, int w_, int ci, int co, int relu, void* stream);
+
 /* wt[ci][tap][co] = w[co][26 - tap][ci] (bf16), the weights of the
  * backward-data convolution. */
 lbm_status nn_conv3d_flip_weights(const void* w, void* wt, int ci, int co, void* stream);
@@ -65,6 +71,15 @@ lbm_status nn_bias_grad_workspace(long long m, int c, size_t* bytes);
  * the workspace and folded in a fixed order (deterministic). */
 lbm_status nn_bias_grad(const float* dy, float* db, void* workspace, size_t workspace_bytes,
                         long long m, int c, void* stream);
+
+/* The backward of an activation fused with what the convolution's backward
+ * needs: dz = relu ? (a > 0 ? da : 0) : da for m voxels of c channels, stored
+ * as bf16 (dz), and db[ch] = sum over voxels of the FP32 dz (float[c]), with
+ * the workspace of nn_bias_grad_workspace(m, c).  Bit-identical to
+ * nn_relu_backward, nn_cast_bf16 and nn_bias_grad.  a (bf16) may be NULL
+ * when relu is 0. */
+lbm_status nn_relu_backward_bias(const float* da, const void* a, void* dz, float* db, void* ws,
+                                 size_t ws_bytes, long long m, int c, int relu, void* stream);
 
 /* a = bf16(relu ? max(z, 0) : z) for n values. */
 lbm_status nn_activation_forward(const float* z, void* a, long long n, int relu, void* stream);

@@ -37,6 +37,17 @@ struct Shape {
   long long m;  // n*d*h*w voxels
 };
 
+// Output of a forward convolution: the FP32 pre-activation y, or (ACT) the
+// BF16 activation a = bf16(relu ? max(y, 0) : y) that the next layer reads,
+// without the FP32 round trip through memory.
+template <bool ACT>
+__device__ __forceinline__ void store_out(void* out, long long i, float v, int relu) {
+  if constexpr (ACT)
+    static_cast<uint16_t*>(out)[i] = f2bf(relu ? fmaxf(v, 0.f) : v);
+  else
+    static_cast<float*>(out)[i] = v;
+}
+
 // voxel index -> (n, z, y, x)
 __device__ __forceinline__ void unflatten(long long m, const Shape& s, int& n, int& z, int& y,
                                           int& x) {
@@ -74,12 +85,12 @@ constexpr int kPad = 8;
 // the tap/channel position of the thread's 8-element granule, advanced
 // incrementally.  The next stage's global loads are issued into registers
 // before the current stage's MFMAs (one stage of prefetch).
-template <int BN>
+template <int BN, bool ACT>
 __global__ __launch_bounds__(256) void conv_fwd_tiled_kernel(const uint16_t* __restrict__ x,
                                                              const uint16_t* __restrict__ w,
                                                              const float* __restrict__ bias,
-                                                             float* __restrict__ y, Shape s,
-                                                             int ci, int co) {
+                                                             void* __restrict__ y, Shape s,
+                                                             int ci, int co, int relu) {
   constexpr int BM = 128, BK = 64, LD = BK + 8;
   constexpr int NBG = BN * BK / 8;          // B granules per stage
   constexpr int NB = (NBG + 255) / 256;     // B granules per thread (at most)
@@ -184,7 +195,7 @@ __global__ __launch_bounds__(256) void conv_fwd_tiled_kernel(const uint16_t* __r
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const long long row = m0 + wv * 32 + r * 16 + (lane >> 4) * 4 + i;
-        if (row < s.m) y[row * co + col] = acc[r][b][i] + bb;
+        if (row < s.m) store_out<ACT>(y, row * co + col, acc[r][b][i] + bb, relu);
       }
   }
 }
@@ -205,12 +216,12 @@ constexpr int kHalo = kHZ * kHY * kHX;  // 600 voxels
 constexpr int kCC = 32;                 // channels per chunk
 constexpr int kHLD = kCC + 8;           // LDS row stride (halfs) of a halo voxel
 
-template <int BN>
+template <int BN, bool ACT>
 __global__ __launch_bounds__(256) void conv_fwd_spatial_kernel(const uint16_t* __restrict__ x,
                                                                const uint16_t* __restrict__ w,
                                                                const float* __restrict__ bias,
-                                                               float* __restrict__ y, Shape s,
-                                                               int ci, int co) {
+                                                               void* __restrict__ y, Shape s,
+                                                               int ci, int co, int relu) {
   constexpr int NT = BN / 16;
   __shared__ __attribute__((aligned(16))) uint16_t Hs[kHalo * kHLD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -297,7 +308,7 @@ __global__ __launch_bounds__(256) void conv_fwd_spatial_kernel(const uint16_t* _
         const int tyy = r >> 3, txx = r & 7;
         const long long v =
             (((long long)bn_ * s.d + z0 + wv) * s.h + y0 + tyy) * s.w + x0 + txx;
-        y[v * co + col] = acc[rt][b][i] + bb;
+        store_out<ACT>(y, v * co + col, acc[rt][b][i] + bb, relu);
       }
   }
 }
@@ -651,6 +662,47 @@ __global__ __launch_bounds__(256) void bias_grad_part_kernel(const float* __rest
 }
 
 constexpr int kBiasSplits = 512;
+
+// The backward of a layer's activation, fused with what the convolution's
+// backward needs from it: dz = (relu ? (a > 0 ? da : 0) : da) stored as BF16
+// (the MFMA operand of both convolution gradients), and the first pass of
+// db = sum_m dz[m][c] over the FP32 dz, in bias_grad_part_kernel's order (so
+// db is bit-identical to nn_bias_grad of the FP32 dz).
+__global__ __launch_bounds__(256) void relu_bwd_bias_part_kernel(
+    const float* __restrict__ da, const uint16_t* __restrict__ a, uint16_t* __restrict__ dzb,
+    float* __restrict__ part, long long m, int c, long long per, int relu) {
+  __shared__ float sh[256];
+  const int G = c <= 256 ? 256 / c : 1;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < m ? beg + per : m;
+  for (int cb = 0; cb < c; cb += 256) {
+    const int tid = threadIdx.x;
+    const int g = c <= 256 ? tid / c : 0;
+    const int ch = c <= 256 ? tid % c : cb + tid;
+    float s = 0.f;
+    if (g < G && ch < c)
+      for (long long v = beg + g; v < end; v += G) {
+        const long long i = v * c + ch;
+        float z = da[i];
+        if (relu && !(bf2f(a[i]) > 0.f)) z = 0.f;
+        dzb[i] = f2bf(z);
+        s += z;
+      }
+    sh[tid] = s;
+    __syncthreads();
+    if (c <= 256) {
+      if (tid < c) {
+        float t = 0.f;
+        for (int q = 0; q < G; ++q) t += sh[q * c + tid];
+        part[(long long)blockIdx.x * c + tid] = t;
+      }
+    } else if (ch < c) {
+      part[(long long)blockIdx.x * c + ch] = s;
+    }
+    __syncthreads();
+    if (c <= 256) break;
+  }
+}
 
 // --------------------------------------------------------------- elementwise
 
@@ -1009,8 +1061,11 @@ __global__ void split_vec_kernel(const float4* __restrict__ dy, float4* __restri
 
 // ------------------------------------------------------------------ C ABI
 
-NN_API lbm_status nn_conv3d_forward(const void* x, const void* w, const float* bias, float* y,
-                                    int n, int d, int h, int wd, int ci, int co, void* stream) {
+namespace {
+
+template <bool ACT>
+lbm_status conv_forward(const void* x, const void* w, const float* bias, void* y, int n, int d,
+                        int h, int wd, int ci, int co, int relu, void* stream) {
   if (!x || !w || !y || bad_shape(n, d, h, wd) || ci < 8 || ci % 8 || co < 1)
     return LBM_ERR_INVALID_ARG;
   const Shape s = shape_of(n, d, h, wd);
@@ -1025,21 +1080,35 @@ NN_API lbm_status nn_conv3d_forward(const void* x, const void* w, const float* b
       tiles * ((co + bn - 1) / bn) >= 128) {
     dim3 sgrid((unsigned)tiles, (unsigned)((co + bn - 1) / bn));
     if (bn == 16)
-      conv_fwd_spatial_kernel<16><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+      conv_fwd_spatial_kernel<16, ACT><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
     else if (bn == 32)
-      conv_fwd_spatial_kernel<32><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+      conv_fwd_spatial_kernel<32, ACT><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
     else
-      conv_fwd_spatial_kernel<64><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+      conv_fwd_spatial_kernel<64, ACT><<<sgrid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
     return check_launch();
   }
   dim3 grid((unsigned)((s.m + 127) / 128), (unsigned)((co + bn - 1) / bn));
   if (bn == 16)
-    conv_fwd_tiled_kernel<16><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+    conv_fwd_tiled_kernel<16, ACT><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
   else if (bn == 32)
-    conv_fwd_tiled_kernel<32><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+    conv_fwd_tiled_kernel<32, ACT><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
   else
-    conv_fwd_tiled_kernel<64><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co);
+    conv_fwd_tiled_kernel<64, ACT><<<grid, 256, 0, st>>>(xx, ww, bias, y, s, ci, co, relu);
   return check_launch();
+}
+
+}  // namespace
+
+NN_API lbm_status nn_conv3d_forward(const void* x, const void* w, const float* bias, float* y,
+                                    int n, int d, int h, int wd, int ci, int co, void* stream) {
+  return conv_forward<false>(x, w, bias, y, n, d, h, wd, ci, co, 0, stream);
+}
+
+NN_API lbm_status nn_conv3d_forward_act(const void* x, const void* w, const float* bias, void* a,
+                                        int n, int d, int h, int wd, int ci, int co, int relu,
+                                        void* stream) {
+  if (relu != 0 && relu != 1) return LBM_ERR_INVALID_ARG;
+  return conv_forward<true>(x, w, bias, a, n, d, h, wd, ci, co, relu, stream);
 }
 
 NN_API lbm_status nn_conv3d_flip_weights(const void* w, void* wt, int ci, int co, void* stream) {
@@ -1152,6 +1221,23 @@ NN_API lbm_status nn_bias_grad(const float* dy, float* db, void* ws, size_t ws_b
   const long long per = (m + splits - 1) / splits;
   bias_grad_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(dy, (float*)ws, m, c,
                                                                           per);
+  fold_splits_kernel<<<grid_for(c), 256, 0, (hipStream_t)stream>>>((const float*)ws, db, c,
+                                                                  (int)splits);
+  return check_launch();
+}
+
+NN_API lbm_status nn_relu_backward_bias(const float* da, const void* a, void* dz, float* db,
+                                       void* ws, size_t ws_bytes, long long m, int c, int relu,
+                                       void* stream) {
+  size_t need = 0;
+  lbm_status st = nn_bias_grad_workspace(m, c, &need);
+  if (st != LBM_OK || !da || !dz || !db || (relu != 0 && relu != 1) || (relu && !a))
+    return LBM_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < need) return LBM_ERR_WORKSPACE;
+  const long long splits = need / ((size_t)c * sizeof(float));
+  const long long per = (m + splits - 1) / splits;
+  relu_bwd_bias_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(
+      da, (const uint16_t*)a, (uint16_t*)dz, (float*)ws, m, c, per, relu);
   fold_splits_kernel<<<grid_for(c), 256, 0, (hipStream_t)stream>>>((const float*)ws, db, c,
                                                                   (int)splits);
   return check_launch();

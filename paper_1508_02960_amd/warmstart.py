@@ -39,6 +39,7 @@ def _nn():
                                   C.c_size_t)
     sig = {
         "nn_conv3d_forward": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
+        "nn_conv3d_forward_act": [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp],
         "nn_conv3d_flip_weights": [vp, vp, i32, i32, vp],
         "nn_conv3d_backward_data": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp],
         "nn_conv3d_backward_weight_workspace": [i32, i32, i32, i32, i32, i32, C.POINTER(sz),
@@ -48,6 +49,7 @@ def _nn():
         "nn_bias_grad": [vp, vp, vp, sz, i64, i32, vp],
         "nn_activation_forward": [vp, vp, i64, i32, vp],
         "nn_relu_backward": [vp, vp, vp, i64, vp],
+        "nn_relu_backward_bias": [vp, vp, vp, vp, vp, sz, i64, i32, i32, vp],
         "nn_cast_bf16": [vp, vp, i64, vp],
         "nn_pool2_forward": [vp, vp, i32, i32, i32, i32, i32, vp],
         "nn_pool2_backward": [vp, vp, i32, i32, i32, i32, i32, vp],
@@ -68,10 +70,12 @@ def _nn():
 
 
 NN_EXPORTS = (
-    "nn_conv3d_forward", "nn_conv3d_flip_weights", "nn_conv3d_backward_data",
+    "nn_conv3d_forward", "nn_conv3d_forward_act", "nn_conv3d_flip_weights",
+    "nn_conv3d_backward_data",
     "nn_conv3d_backward_weight_workspace", "nn_conv3d_backward_weight", "nn_bias_grad",
     "nn_bias_grad_workspace",
-    "nn_activation_forward", "nn_relu_backward", "nn_cast_bf16", "nn_pool2_forward",
+    "nn_activation_forward", "nn_relu_backward", "nn_relu_backward_bias", "nn_cast_bf16",
+    "nn_pool2_forward",
     "nn_pool2_backward", "nn_upsample2_forward", "nn_upsample2_backward", "nn_concat_channels",
     "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam",
 )
@@ -139,26 +143,40 @@ class Conv:
                                      self.ci, self.co, self.ctx.stream), "conv forward")
         return y
 
-    def backward(self, x_bf, dy32, shape, need_dx=True):
+    def forward_act(self, x_bf, shape, relu=True):
+        """bf16(relu(conv(x))): the convolution and the activation in one kernel."""
+        n, d, h, w = shape
+        a = self.ctx.bf(n, d, h, w, self.co)
+        _chk(_nn().nn_conv3d_forward_act(_p(x_bf), _p(self.wb), _p(self.b), _p(a), n, d, h, w,
+                                         self.ci, self.co, 1 if relu else 0, self.ctx.stream),
+             "conv forward + activation")
+        return a
+
+    def backward(self, x_bf, dy32, shape, need_dx=True, act=None):
+        """Weight and bias gradients (and the input gradient if need_dx) for
+        the FP32 gradient dy32 of the layer's output; act is the stored BF16
+        activation of a ReLU layer (its backward, the BF16 cast and the bias
+        gradient are one kernel), None for a linear layer."""
         lib = _nn()
         n, d, h, w = shape
         m = n * d * h * w
+        t = self.ctx.torch
         dy = self.ctx.bf(n, d, h, w, self.co)
-        _chk(lib.nn_cast_bf16(_p(dy32), _p(dy), dy32.numel(), self.ctx.stream), "cast")
+        bb = C.c_size_t()
+        _chk(lib.nn_bias_grad_workspace(m, self.co, C.byref(bb)), "bias ws")
+        bws = t.empty(int(bb.value), dtype=t.uint8, device=self.ctx.dev)
+        _chk(lib.nn_relu_backward_bias(_p(dy32), None if act is None else _p(act), _p(dy),
+                                       _p(self.gb), _p(bws), bb.value, m, self.co,
+                                       0 if act is None else 1, self.ctx.stream),
+             "activation backward + bias grad")
         nbytes = C.c_size_t()
         sp = C.c_int()
         _chk(lib.nn_conv3d_backward_weight_workspace(n, d, h, w, self.ci, self.co,
                                                      C.byref(nbytes), C.byref(sp)), "ws")
-        ws = self.ctx.torch.empty(int(nbytes.value), dtype=self.ctx.torch.uint8,
-                                  device=self.ctx.dev)
+        ws = t.empty(int(nbytes.value), dtype=t.uint8, device=self.ctx.dev)
         _chk(lib.nn_conv3d_backward_weight(_p(x_bf), _p(dy), _p(self.gw), _p(ws), nbytes.value,
                                            n, d, h, w, self.ci, self.co, self.ctx.stream),
              "conv backward weight")
-        bb = C.c_size_t()
-        _chk(lib.nn_bias_grad_workspace(m, self.co, C.byref(bb)), "bias ws")
-        bws = self.ctx.torch.empty(int(bb.value), dtype=self.ctx.torch.uint8, device=self.ctx.dev)
-        _chk(lib.nn_bias_grad(_p(dy32), _p(self.gb), _p(bws), bb.value, m, self.co,
-                              self.ctx.stream), "bias grad")
         if not need_dx:
             return None
         dx = self.ctx.f32(n, d, h, w, self.ci)
@@ -200,12 +218,6 @@ class UNet:
         return sum(l.n_params() for l in self.layers())
 
     # -------------------------------------------------------------- passes
-    def _act(self, z, relu=True):
-        a = self.ctx.bf(*z.shape)
-        _chk(_nn().nn_activation_forward(_p(z), _p(a), z.numel(), 1 if relu else 0,
-                                         self.ctx.stream), "activation")
-        return a
-
     def forward(self, x_bf):
         """x_bf: bf16 (n, d, h, w, 8), d, h, w divisible by 8.  Returns the
         FP32 output (n, d, h, w, 8) and keeps what the backward pass needs."""
@@ -222,7 +234,7 @@ class UNet:
                 _chk(lib.nn_pool2_forward(_p(inp), _p(p), pn, pd, ph, pw, conv.ci, s), "pool")
                 inp = p
             self.cache[f"in{lvl}"] = inp
-            e.append(self._act(conv.forward(inp, shapes[lvl])))
+            e.append(conv.forward_act(inp, shapes[lvl]))
             inp = e[-1]
         cur = e[3]
         for j, conv in enumerate(self.dec):
@@ -236,7 +248,7 @@ class UNet:
             _chk(lib.nn_concat_channels(_p(up), _p(e[lvl]), _p(cat), m, ccur, self.widths[lvl], s),
                  "concat")
             self.cache[f"cat{lvl}"] = cat
-            cur = self._act(conv.forward(cat, shapes[lvl]))
+            cur = conv.forward_act(cat, shapes[lvl])
             self.cache[f"d{lvl}"] = cur
         self.cache["e"] = e
         out = self.head.forward(cur, shapes[0])
@@ -254,10 +266,7 @@ class UNet:
         for j, conv in enumerate(self.dec):
             lvl = j  # backward goes 0, 1, 2 through decoder levels
             conv = self.dec[2 - lvl]
-            act = c[f"d{lvl}"]
-            dz = self.ctx.f32(*act.shape)
-            _chk(lib.nn_relu_backward(_p(g), _p(act), _p(dz), act.numel(), s), "relu backward")
-            dcat = conv.backward(c[f"cat{lvl}"], dz, shapes[lvl])
+            dcat = conv.backward(c[f"cat{lvl}"], g, shapes[lvl], act=c[f"d{lvl}"])
             ccur = self.widths[lvl + 1]
             m = int(np.prod(shapes[lvl]))
             dup = self.ctx.f32(*shapes[lvl], ccur)
@@ -271,12 +280,9 @@ class UNet:
         # g: gradient of e[3]; down the encoder
         for lvl in (3, 2, 1, 0):
             conv = self.enc[lvl]
-            act = e[lvl]
             if lvl < 3:
                 _chk(lib.nn_add(_p(g), _p(skip_grads[lvl]), g.numel(), s), "add")
-            dz = self.ctx.f32(*act.shape)
-            _chk(lib.nn_relu_backward(_p(g), _p(act), _p(dz), act.numel(), s), "relu backward")
-            dinp = conv.backward(c[f"in{lvl}"], dz, shapes[lvl], need_dx=lvl > 0)
+            dinp = conv.backward(c[f"in{lvl}"], g, shapes[lvl], need_dx=lvl > 0, act=e[lvl])
             if lvl > 0:
                 g = self.ctx.f32(*shapes[lvl - 1], conv.ci)
                 pn, pd, ph, pw = shapes[lvl - 1]

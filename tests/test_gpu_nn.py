@@ -70,6 +70,14 @@ def test_conv_forward_backward_match_reference(ctx, shape, ci, co):
     assert lib.nn_conv3d_forward(W._p(xd), W._p(wb), W._p(bd), W._p(y), n, d, h, wd, ci, co,
                                  ctx.stream) == 0
     assert rel(_host(y), R.conv3d(x, w, b)) < 1e-5
+    # the fused activation equals the two-step form bit for bit
+    for relu in (1, 0):
+        a_ref = ctx.bf(n, d, h, wd, co)
+        assert lib.nn_activation_forward(W._p(y), W._p(a_ref), y.numel(), relu, ctx.stream) == 0
+        a = ctx.bf(n, d, h, wd, co)
+        assert lib.nn_conv3d_forward_act(W._p(xd), W._p(wb), W._p(bd), W._p(a), n, d, h, wd, ci,
+                                         co, relu, ctx.stream) == 0
+        assert ctx.torch.equal(a.view(ctx.torch.int16), a_ref.view(ctx.torch.int16)), relu
     dx_ref, dw_ref, db_ref = R.conv3d_backward(x, w, dy)
     if co % 8 == 0:
         wt = ctx.bf(ci, 27, co)
@@ -142,6 +150,41 @@ def test_pool_up_concat_split_relu(ctx, c):
     assert lib.nn_relu_backward(W._p(_f_dev(ctx, da)), W._p(act), W._p(dz), ne, s) == 0
     assert np.allclose(_host(dz), np.where(R.bf16(np.maximum(z, 0)) > 0,
                                            da.astype(np.float32), 0))
+
+
+@pytest.mark.parametrize("m,c", [(3000, 32), (777, 6), (513, 300)])
+def test_relu_backward_bias_fused(ctx, m, c):
+    """nn_relu_backward_bias equals nn_relu_backward, nn_cast_bf16 and
+    nn_bias_grad bit for bit (c = 300: the wide-channel branch), with and
+    without the ReLU; db also against the FP64 sum."""
+    import ctypes as C
+
+    t = ctx.torch
+    rng = np.random.default_rng(m + c)
+    lib = W._nn()
+    s = ctx.stream
+    da = _f_dev(ctx, rng.standard_normal((m, c)))
+    act = _bf_dev(ctx, np.maximum(rng.standard_normal((m, c)), 0))
+    bb = C.c_size_t()
+    assert lib.nn_bias_grad_workspace(m, c, C.byref(bb)) == 0
+    ws = t.empty(bb.value, dtype=t.uint8, device=ctx.dev)
+    for relu in (1, 0):
+        dz32 = ctx.f32(m, c)
+        if relu:
+            assert lib.nn_relu_backward(W._p(da), W._p(act), W._p(dz32), m * c, s) == 0
+        else:
+            dz32.copy_(da)
+        dz_ref, db_ref = ctx.bf(m, c), ctx.f32(c)
+        assert lib.nn_cast_bf16(W._p(dz32), W._p(dz_ref), m * c, s) == 0
+        assert lib.nn_bias_grad(W._p(dz32), W._p(db_ref), W._p(ws), bb.value, m, c, s) == 0
+        dz, db = ctx.bf(m, c), ctx.f32(c)
+        assert lib.nn_relu_backward_bias(W._p(da), W._p(act) if relu else None, W._p(dz),
+                                         W._p(db), W._p(ws), bb.value, m, c, relu, s) == 0
+        assert t.equal(dz.view(t.int16), dz_ref.view(t.int16)), relu
+        assert t.equal(db, db_ref), relu
+        assert rel(_host(db), _host(dz32).sum(axis=0)) < 1e-5
+    assert lib.nn_relu_backward_bias(W._p(da), None, W._p(dz), W._p(db), W._p(ws), bb.value,
+                                     m, c, 1, s) == 1  # ReLU without the activation
 
 
 def test_mse_and_adam(ctx):
