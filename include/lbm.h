@@ -123,7 +123,8 @@ typedef struct {
   int64_t n_links;         /* wall links (fluid cell, direction into solid)     */
   int64_t n_fallback;      /* links whose second fluid node is solid (CLI->SBB) */
   int64_t workspace_bytes; /* device bytes lbm_bind needs                       */
-  int64_t plane_stride;    /* elements between direction planes on the device   */
+  int64_t state_elems;     /* elements of one device state buffer (19 per cell  */
+                           /* address, addresses padded to whole runs)          */
   double nu;               /* kinematic viscosity (tau - 1/2)/3                 */
   double omega_plus;       /* 1/tau                                             */
   double omega_minus;      /* TRT antisymmetric rate from Lambda                */
@@ -351,8 +352,9 @@ lbm_status lbm_destroy(lbm_domain d);
  *   LBM_PROBE_COPY     copies n bytes from src to dst
  *   LBM_PROBE_GATHER19 the step's pull pattern on an all-fluid periodic cube
  *                      of edge n (multiple of 16, at most 1024): src and dst
- *                      hold 19 FP32 planes of n^3 values in 16 x 4 tiles;
- *                      reads and writes 2 * 76 n^3 bytes
+ *                      hold 19 FP32 values for each of n^3 cells in 16 x 4
+ *                      tiles, each tile's values as 19 runs of 64 (one per
+ *                      direction); reads and writes 2 * 76 n^3 bytes
  * Errors: LBM_ERR_INVALID_ARG for an unknown kind, a bad size, NULL or
  * misaligned buffers; LBM_ERR_DEVICE if the launch fails. */
 typedef enum {

@@ -63,16 +63,17 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(const v4f* __restrict__ 
 }
 
 // The step kernel's access pattern with nothing else: an all-fluid periodic
-// cube of edge n in the step's layout for large states (16 x 4 tiles, n a
-// multiple of 16), 19 FP32 planes of n^3 values; dst[k](x) = src[k](x - e_k),
-// workgroups of 8 wavefronts over consecutive tiles of a z plane,
-// non-temporal stores.
+// cube of edge n in the step's layout for large FP32 states (16 x 4 tiles, n
+// a multiple of 16; the 19 values of a tile stored as 19 runs of 64, one per
+// direction); dst[k](x) = src[k](x - e_k), workgroups of 8 wavefronts over
+// consecutive tiles of a z plane, non-temporal stores.
 __constant__ int kEx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 __constant__ int kEy[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
 __constant__ int kEz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
 
 __device__ __forceinline__ int xpart(int x) { return ((x >> 4) << 6) | (x & 15); }
 __device__ __forceinline__ int ypart(int y, int ntx) { return (y >> 2) * (ntx << 6) + ((y & 3) << 4); }
+__device__ __forceinline__ long long run_slot(int k, long long a) { return ((a >> 6) * 19 + k) * 64 + (a & 63); }
 
 __global__ __launch_bounds__(512) void gather19_kernel(const float* __restrict__ src,
                                                        float* __restrict__ dst, int n) {
@@ -81,19 +82,19 @@ __global__ __launch_bounds__(512) void gather19_kernel(const float* __restrict__
   if (tile >= ntx * nty) return;
   const int l = threadIdx.x;
   const int x = ((tile % ntx) << 4) + (l & 15), y = ((tile / ntx) << 2) + (l >> 4), z = blockIdx.z;
-  const long long st = (long long)plane * n;
   // wrapped neighbour coordinates as address parts (index 0: -1, 1: 0, 2: +1)
   const int xs[3] = {xpart(x == 0 ? n - 1 : x - 1), xpart(x), xpart(x == n - 1 ? 0 : x + 1)};
   const int ys[3] = {ypart(y == 0 ? n - 1 : y - 1, ntx), ypart(y, ntx),
                      ypart(y == n - 1 ? 0 : y + 1, ntx)};
-  const int zs[3] = {(z == 0 ? n - 1 : z - 1) * plane, z * plane, (z == n - 1 ? 0 : z + 1) * plane};
-  const int c = xs[1] + ys[1] + zs[1];
+  const long long zs[3] = {(long long)(z == 0 ? n - 1 : z - 1) * plane, (long long)z * plane,
+                           (long long)(z == n - 1 ? 0 : z + 1) * plane};
+  const long long c = xs[1] + ys[1] + zs[1];
   float v[19];
 #pragma unroll
   for (int k = 0; k < 19; ++k)
-    v[k] = src[k * st + xs[1 - kEx[k]] + ys[1 - kEy[k]] + zs[1 - kEz[k]]];
+    v[k] = src[run_slot(k, xs[1 - kEx[k]] + ys[1 - kEy[k]] + zs[1 - kEz[k]])];
 #pragma unroll
-  for (int k = 0; k < 19; ++k) __builtin_nontemporal_store(v[k], &dst[k * st + c]);
+  for (int k = 0; k < 19; ++k) __builtin_nontemporal_store(v[k], &dst[run_slot(k, c)]);
 }
 
 }  // namespace

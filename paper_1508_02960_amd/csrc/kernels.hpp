@@ -1,18 +1,19 @@
 // HIP kernels of the D3Q19 hot path for gfx950 (MI355X).
 //
 // Data layout in HBM: two population buffers (A: current post-collision
-// state, B: next), each 19 direction planes of `stride` elements, the plane
-// of direction k holding g_k = f_k - w_k of every cell.  Cells are stored in
-// tiled order (Tiling): each z plane is cut into tiles of 64 cells, one
-// wavefront each.  States well beyond the last-level cache use 16 x 4 tiles,
-// so a 128-byte line of a plane covers a compact patch of cells rather than
-// a stretch of one row, and where sphere surfaces cut the lines, fewer of
-// them are fetched for a few fluid cells; smaller states use 64 x 1 tiles,
-// i.e. plain rows.  A uint8 class per cell
-// says whether the cell is solid and whether it has wall links; the uint32
-// flag word of a cell with links marks the directions whose pull source is
+// state, B: next) of g_k = f_k - w_k, 19 values per cell address, stored in
+// runs (Tiling::slot): a run of 64 or 128 consecutive addresses holds its 19
+// directions one after the other.  Cells are stored in tiled order
+// (Tiling): each z plane is cut into tiles of 64 cells, one wavefront each.
+// States well beyond the last-level cache use compact tiles (16 x 4, or
+// 32 x 2 for 16-bit values), so a 128-byte line covers a compact patch of
+// cells rather than a stretch of one row, and where sphere surfaces cut the
+// lines, fewer of them are fetched for a few fluid cells; smaller states use
+// 64 x 1 tiles, i.e. plain rows.  A uint8 class per cell says whether the
+// cell is solid and whether it has wall links; the uint32 flag word of a
+// cell with links marks the directions whose pull source is
 // solid.  For such a wall link the otherwise unused slot of the solid source
-// node in plane k holds the CLI coefficient a = (1-2q)/(1+2q) (0 for
+// node in direction k holds the CLI coefficient a = (1-2q)/(1+2q) (0 for
 // fallback links), written once at bind time into both buffers.  In batches,
 // solid cells next to fluid cells may copy their link slots and write zeros
 // elsewhere (whole-line writes, solid_stores); otherwise solid cells are not
@@ -51,6 +52,7 @@ struct Tiling {
   int ntx;               // tiles per tile row (padded nx / tile width)
   int nty;               // tile rows per plane
   int plane;             // cells per z plane including padding: ntx * nty * 64
+  int run_log2;          // state buffers: runs of 2^run_log2 consecutive addresses
   __host__ __device__ int xpart(int x) const {
     return ((x >> tw_log2) << 6) | (x & ((1 << tw_log2) - 1));
   }
@@ -65,6 +67,14 @@ struct Tiling {
     const int t = r >> 6, l = r & 63;
     x = ((t % ntx) << tw_log2) + (l & ((1 << tw_log2) - 1));
     y = ((t / ntx) << th_log2) + (l >> tw_log2);
+  }
+  // Index of direction k of the cell at address a in a state buffer.  The
+  // addresses are cut into runs of 2^run_log2 (one tile, or the two tiles of
+  // a two-cell wavefront) and each run stores its 19 directions one after
+  // the other, so a wavefront's load or store of one direction is one
+  // contiguous run and all 19 lie within 19 runs of each other.
+  __host__ __device__ long long slot(int k, long long a) const {
+    return ((((a >> run_log2) * kQ) + k) << run_log2) + (a & ((1LL << run_log2) - 1));
   }
   // address of the cell with row-major index c = x + nx (y + ny z)
   __host__ __device__ int from_linear(long long c) const {
@@ -81,7 +91,6 @@ constexpr uint8_t kClsLinks = 2;  // the cell's flag word has link bits
 struct StepParams {
   Tiling t;
   int nx, ny, nz;
-  long long stride;   // elements between direction planes
   double jump_axis;   // w_axis * delta_rho
   double jump_diag;   // w_diag * delta_rho
   double omega_p;     // 1/tau (SRT, TRT symmetric, MRT viscous modes)
@@ -501,9 +510,9 @@ __device__ __forceinline__ FarNode far_node(const StepParams& p, int x, int y, i
 
 // Population kk at a far node, with the jump of a crossing read.
 template <typename S, typename C>
-__device__ __forceinline__ C far_value(const S* __restrict__ src, long long st,
-                                       const StepParams& p, FarNode f, int kk) {
-  C v = (C)Storage<S>::to_float(src[kk * st + f.c]);
+__device__ __forceinline__ C far_value(const S* __restrict__ src, const StepParams& p, FarNode f,
+                                       int kk) {
+  C v = (C)Storage<S>::to_float(src[p.t.slot(kk, f.c)]);
   const C jw = (C)(wclass(kk) == 1 ? p.jump_axis : p.jump_diag);
   if (f.cross > 0) v -= jw;
   if (f.cross < 0) v += jw;
@@ -513,13 +522,13 @@ __device__ __forceinline__ C far_value(const S* __restrict__ src, long long st,
 // Density deviation and velocity of the stored (post-collision) state at
 // cell c; collision conserves both, so these are the moments at time t_n.
 template <typename S, typename C>
-__device__ __forceinline__ void stored_moments(const S* __restrict__ src, long long st, int c,
+__device__ __forceinline__ void stored_moments(const S* __restrict__ src, const Tiling& t, int c,
                                                C& drho, C (&u)[3]) {
   drho = (C)0;
   u[0] = u[1] = u[2] = (C)0;
 #pragma unroll
   for (int kk = 0; kk < kQ; ++kk) {
-    const C v = (C)Storage<S>::to_float(src[kk * st + c]);
+    const C v = (C)Storage<S>::to_float(src[t.slot(kk, c)]);
     drho += v;
     u[0] += (C)kLat.ex[kk] * v;
     u[1] += (C)kLat.ey[kk] * v;
@@ -543,7 +552,6 @@ template <typename S, typename C>
 __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __restrict__ flags,
                                 const StepParams& p, int x, int y, int z, int c, int k, C q,
                                 uint32_t fl, const C (&m1)[4], C pulled_j, C own_j, C own_k) {
-  const long long st = p.stride;
   const int j = kLat.opp[k];
   const FarNode n2 = far_node(p, x, y, z, k, 1);
   const FarNode n3 = far_node(p, x, y, z, k, 2);
@@ -582,9 +590,9 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       if (q < (C)0.5)
         return q * (one + two * q) * own_j +
                (one - (C)4 * q * q) * f2_j -
-               q * (one - two * q) * far_value<S, C>(src, st, p, n3, j);
+               q * (one - two * q) * far_value<S, C>(src, p, n3, j);
       return (two * q - one) / q * own_k + own_j / (q * (two * q + one)) +
-             (one - two * q) / (two * q + one) * far_value<S, C>(src, st, p, n2, k);
+             (one - two * q) / (two * q + one) * far_value<S, C>(src, p, n2, k);
     case kRuleIEBB: {
       const C drho1 = m1[0], u1[3] = {m1[1], m1[2], m1[3]};
       C ubf[3], X;
@@ -592,7 +600,7 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       if (q < (C)0.5) {
         if (!f2) return own_j;
         C d2;
-        stored_moments<S, C>(src, st, n2.c, d2, ubf);
+        stored_moments<S, C>(src, p.t, n2.c, d2, ubf);
         X = (two * q - one) / (tau - two);
       } else {
         const C f = one - (C)3 / (two * q);
@@ -612,8 +620,8 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       if (!f2) return own_j;
       const C d = (one + q) * (one + q);
       const C k1 = (one - two * q - two * q * q) / d, k2 = q * q / d;
-      return k1 * f2_j + k2 * far_value<S, C>(src, st, p, n3, j) -
-             k1 * own_k - k2 * far_value<S, C>(src, st, p, n2, k) + own_j;
+      return k1 * f2_j + k2 * far_value<S, C>(src, p, n3, j) -
+             k1 * own_k - k2 * far_value<S, C>(src, p, n2, k) + own_j;
     }
     default:
       return own_j;
@@ -748,12 +756,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
   n.zs[1] = z * plane;
   n.zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
 
-  const long long st = p.stride;
   C g[kQ];
   // pull: direction k arrives from x - e_k (raw stored values)
 #pragma unroll
   for (int k = 0; k < kQ; ++k)
-    g[k] = (C)St::to_float(src[k * st + n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])]);
+    g[k] = (C)St::to_float(src[p.t.slot(k, n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k]))]);
 
   // wall links: the pulled raw value is the stored coefficient a (CLI) or
   // the wall distance q (general rules)
@@ -765,11 +772,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
     // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
     // come from the same values.
 #pragma unroll
-    for (int k = 1; k < kQ; ++k) own[k] = src[k * st + c];
+    for (int k = 1; k < kQ; ++k) own[k] = src[p.t.slot(k, c)];
     if constexpr (WALL == kGEN) {
       C m1[4] = {(C)0, (C)0, (C)0, (C)0};
       if (p.wall == kRuleIEBB) {
-        own[0] = src[c];
+        own[0] = src[p.t.slot(0, c)];
 #pragma unroll
         for (int kk = 0; kk < kQ; ++kk) {
           const C v = (C)St::to_float(own[kk]);
@@ -804,12 +811,12 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
 // partly written lines cost far more than their bytes (a batch of 64^3 cells
 // holding spheres of diameter 50 steps 17% faster with mode 1).
 template <typename S>
-__device__ __forceinline__ void solid_node(const S* __restrict__ src, S (&out)[kQ], long long st,
-                                           int c, uint32_t fl) {
+__device__ __forceinline__ void solid_node(const S* __restrict__ src, S (&out)[kQ],
+                                           const Tiling& t, int c, uint32_t fl) {
   out[0] = Storage<S>::from_float(0);
 #pragma unroll
   for (int k = 1; k < kQ; ++k)
-    out[k] = (fl & (1u << k)) ? src[k * st + c] : Storage<S>::from_float(0);
+    out[k] = (fl & (1u << k)) ? src[t.slot(k, c)] : Storage<S>::from_float(0);
 }
 
 // Whether this lane stores, given the fluid lanes of its wavefront: fluid
@@ -842,14 +849,14 @@ __device__ __forceinline__ void nontemporal_store(S v, S* p) {
 }
 
 template <typename S, bool NT>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[kQ], long long st,
-                                           int c) {
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[kQ],
+                                           const Tiling& t, int c) {
 #pragma unroll
   for (int k = 0; k < kQ; ++k) {
     if constexpr (NT)
-      nontemporal_store(out[k], &dst[k * st + c]);
+      nontemporal_store(out[k], &dst[t.slot(k, c)]);
     else
-      dst[k * st + c] = out[k];
+      dst[t.slot(k, c)] = out[k];
   }
 }
 
@@ -922,7 +929,6 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
   using C = typename ComputeOf<S>::type;
   const int z = blockIdx.z;
   const TileCell tc = step_tile_cell(p, z);
-  const long long st = p.stride;
   const uint8_t k = tc.inside ? cls[tc.c] : kClsSolid;
   if constexpr (!RED) {
     if (k & kClsSolid) return;
@@ -930,7 +936,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
     S out[kQ];
     C mom[5];
     update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
-    store_node<S, NT>(dst, out, st, tc.c);
+    store_node<S, NT>(dst, out, p.t, tc.c);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (!(k & kClsSolid)) {
@@ -938,7 +944,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
       S out[kQ];
       C mom[5];
       update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
-      store_node<S, NT>(dst, out, st, tc.c);
+      store_node<S, NT>(dst, out, p.t, tc.c);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
       v[0] = ux;
@@ -1024,7 +1030,6 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
   const Tiling& t = p.t;
   const int z = blockIdx.z;
   const PairCell pc = pair_cell(p);
-  const long long st = p.stride;
   const int c = pc.a + z * t.plane;  // cell A
   const uint32_t cl2 = pc.inside ? (uint32_t)(*reinterpret_cast<const uint16_t*>(cls + c))
                                  : (uint32_t)(kClsSolid | (kClsSolid << 8));
@@ -1060,11 +1065,10 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
     for (int k = 0; k < kQ; ++k) {
       const int ex = kLat.ex[k];
       const int row = ys[1 - kLat.ey[k]] + zs[1 - kLat.ez[k]];
-      const uint32_t* sk = s32 + ((k * st) >> 1);
       const int a0 = row_reads ? xs_0 + row : 0;
-      raw[k] = sk[a0 >> 1];
-      if (ex == 1) edge[k] = sk[(row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
-      if (ex == -1) edge[k] = sk[(row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
+      raw[k] = s32[t.slot(k, a0) >> 1];
+      if (ex == 1) edge[k] = s32[t.slot(k, row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
+      if (ex == -1) edge[k] = s32[t.slot(k, row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
     }
     // Boundary pairs: both flag words and the pair's own words, requested
     // with the pulls (one memory round trip): wall rules of link cells, and
@@ -1076,7 +1080,7 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
     if (links) {
       flw = *reinterpret_cast<const uint2*>(flags + c);
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) own_w[k] = s32[(k * st + c) >> 1];
+      for (int k = 0; k < kQ; ++k) own_w[k] = s32[t.slot(k, c) >> 1];
     }
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
@@ -1143,7 +1147,7 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
         uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
-          uint32_t* q = d32 + ((k * st + c) >> 1);
+          uint32_t* q = d32 + (t.slot(k, c) >> 1);
           if constexpr (NT)
             __builtin_nontemporal_store(outw[k], q);
           else
@@ -1181,8 +1185,10 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
   if (!active[b]) return;
   const StepParams p = cells[b];
   const long long off = (long long)b * cell_size;
-  const S* s = src + off;
-  S* d = dst + off;
+  // cell b's addresses start at off, a whole number of runs: its state
+  // starts at kQ * off
+  const S* s = src + off * kQ;
+  S* d = dst + off * kQ;
   const uint8_t* cl = cls + off;
   const uint32_t* f = flags + off;
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1198,10 +1204,10 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     S out[kQ];
     C mom[5];
     if (solid)
-      solid_node<S>(s, out, p.stride, c, fl);
+      solid_node<S>(s, out, p.t, c, fl);
     else
       update_node<S, COLL, WALL>(s, out, f, p, tc.x, tc.y, z, c, fl, mom);
-    if (tc.inside) store_node<S, NT>(d, out, p.stride, c);
+    if (tc.inside) store_node<S, NT>(d, out, p.t, c);
     if (solid) continue;
     if constexpr (RED) {
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
@@ -1330,14 +1336,14 @@ __global__ void fill_int_kernel(int* __restrict__ a, int n, int v) {
 template <typename S>
 __global__ void batch_align_kernel(S* __restrict__ to, const S* __restrict__ from,
                                    const CellStatus* __restrict__ st, int to_parity,
-                                   long long cell_size, long long stride, int n_cells) {
+                                   long long cell_size, Tiling t, int n_cells) {
   const long long total = (long long)n_cells * cell_size;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(i / cell_size);
     if (st[b].status == 0 || st[b].parity == to_parity) continue;
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) to[k * stride + i] = from[k * stride + i];
+    for (int k = 0; k < kQ; ++k) to[t.slot(k, i)] = from[t.slot(k, i)];
   }
 }
 
@@ -1362,7 +1368,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const doub
 template <typename S>
 __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __restrict__ src,
                                                                    const uint32_t* __restrict__ flags,
-                                                                   long long stride, int naddr,
+                                                                   Tiling t, int naddr,
                                                                    double sigma,
                                                                    double* __restrict__ partials) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1371,7 +1377,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __re
     if (flags[c] & kSolid) continue;
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(src[k * stride + c], k, sigma);
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(src[t.slot(k, c)], k, sigma);
     double rho, ux, uy, uz;
     moments<double>(g, rho, ux, uy, uz);
     const double u2 = ux * ux + uy * uy + uz * uz;
@@ -1398,7 +1404,6 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
                                                            double* __restrict__ partials) {
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int naddr = p.t.plane * p.nz;
-  const long long st = p.stride;
   for (long long cc = blockIdx.x * kRedThreads + threadIdx.x; cc < naddr;
        cc += (long long)gridDim.x * kRedThreads) {
     const int c = (int)cc;
@@ -1410,7 +1415,7 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
     if constexpr (WALL == kGEN) {
       if (p.wall == kRuleIEBB) {
         double u1[3];
-        stored_moments<S, double>(src, st, c, m1[0], u1);
+        stored_moments<S, double>(src, p.t, c, m1[0], u1);
         m1[1] = u1[0];
         m1[2] = u1[1];
         m1[3] = u1[2];
@@ -1419,29 +1424,29 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
     for (int k = 1; k < kQ; ++k) {
       if (!(fl & (1u << k))) continue;
       const int j = kLat.opp[k];
-      const double own_j = stored_to_g<S>(src[j * st + c], j, p.sigma);
+      const double own_j = stored_to_g<S>(src[p.t.slot(j, c)], j, p.sigma);
       double back = own_j;
       if constexpr (WALL == kGEN) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double q = (double)Storage<S>::to_float(src[k * st + p.t.at(sx, sy, sz)]);
+        const double q = (double)Storage<S>::to_float(src[p.t.slot(k, p.t.at(sx, sy, sz))]);
         const FarNode n2 = far_node(p, x, y, z, k, 1);
         back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1,
-                                             (double)Storage<S>::to_float(src[j * st + n2.c]),
-                                             (double)Storage<S>::to_float(src[j * st + c]),
-                                             (double)Storage<S>::to_float(src[k * st + c]));
+                                             (double)Storage<S>::to_float(src[p.t.slot(j, n2.c)]),
+                                             (double)Storage<S>::to_float(src[p.t.slot(j, c)]),
+                                             (double)Storage<S>::to_float(src[p.t.slot(k, c)]));
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double a = (double)Storage<S>::to_float(src[k * st + p.t.at(sx, sy, sz)]);
+        const double a = (double)Storage<S>::to_float(src[p.t.slot(k, p.t.at(sx, sy, sz))]);
         const int tx = x + kLat.ex[k];
         const int fx = (tx + p.nx) % p.nx, fy = (y + kLat.ey[k] + p.ny) % p.ny,
                   fz = (z + kLat.ez[k] + p.nz) % p.nz;
-        double far_j = stored_to_g<S>(src[j * st + p.t.at(fx, fy, fz)], j, p.sigma);
+        double far_j = stored_to_g<S>(src[p.t.slot(j, p.t.at(fx, fy, fz))], j, p.sigma);
         const double jw = kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag;
         if (tx >= p.nx) far_j -= jw;
         if (tx < 0) far_j += jw;
-        back = a * far_j - a * stored_to_g<S>(src[k * st + c], k, p.sigma) + own_j;
+        back = a * far_j - a * stored_to_g<S>(src[p.t.slot(k, c)], k, p.sigma) + own_j;
       }
       const double tot = (own_j + kLat.w[j]) + (back + kLat.w[k]);
       v[0] += kLat.ex[j] * tot;
@@ -1500,27 +1505,27 @@ __device__ __forceinline__ int addr_of(const Tiling& t, long long c, long long c
   return (int)(b * cell_addrs) + t.from_linear(c - b * cell_cells);
 }
 
-// One direction plane k, cells [c0, c0 + n) in row-major order, to/from a
+// Direction k, cells [c0, c0 + n) in row-major order, to/from a
 // double staging buffer (values are g_k; 16-bit storage is decoded / encoded
 // with sigma).
 template <typename S>
-__global__ void get_plane_kernel(const S* __restrict__ plane, const uint32_t* __restrict__ flags,
+__global__ void get_plane_kernel(const S* __restrict__ buf, const uint32_t* __restrict__ flags,
                                  Tiling t, long long cell_cells, int cell_addrs, int k,
                                  double sigma, int c0, int n, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
-  out[i] = (flags[a] & kSolid) ? 0.0 : stored_to_g<S>(plane[a], k, sigma);
+  out[i] = (flags[a] & kSolid) ? 0.0 : stored_to_g<S>(buf[t.slot(k, a)], k, sigma);
 }
 
 template <typename S>
-__global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restrict__ flags,
+__global__ void set_plane_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
                                  Tiling t, long long cell_cells, int cell_addrs, int k,
                                  double sigma, int c0, int n, const double* __restrict__ in) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
-  if (!(flags[a] & kSolid)) plane[a] = g_to_stored<S>(in[i], k, sigma);
+  if (!(flags[a] & kSolid)) buf[t.slot(k, a)] = g_to_stored<S>(in[i], k, sigma);
 }
 
 // g = g^eq(drho, u) for fluid cells [c0, c0 + n) (row-major order); stage =
@@ -1529,7 +1534,7 @@ __global__ void set_plane_kernel(S* __restrict__ plane, const uint32_t* __restri
 template <typename S>
 __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
                                Tiling t, long long cell_cells, int cell_addrs,
-                               long long stride, double sigma, int c0, int n,
+                               double sigma, int c0, int n,
                                const double* __restrict__ stage) {
   using C = typename ComputeOf<S>::type;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1546,14 +1551,14 @@ __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__
   LBM_EQ(17) LBM_EQ(18)
 #undef LBM_EQ
 #pragma unroll
-  for (int k = 0; k < kQ; ++k) buf[k * stride + c] = g_to_stored<S>((double)g[k], k, sigma);
+  for (int k = 0; k < kQ; ++k) buf[t.slot(k, c)] = g_to_stored<S>((double)g[k], k, sigma);
 }
 
 // drho, u of cells [c0, c0 + n) (row-major order) into stage (drho | ux |
 // uy | uz blocks).
 template <typename S>
 __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                             Tiling t, long long cell_cells, int cell_addrs, long long stride,
+                             Tiling t, long long cell_cells, int cell_addrs,
                              double sigma, int c0, int n, double* __restrict__ stage) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1562,7 +1567,7 @@ __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restri
   if (!(flags[c] & kSolid)) {
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(buf[k * stride + c], k, sigma);
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(buf[t.slot(k, c)], k, sigma);
     moments<double>(g, rho, ux, uy, uz);
   }
   stage[i] = rho;
@@ -1575,13 +1580,13 @@ __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restri
 // a value leaves the normal range); used to move the 16-bit storage scale.
 template <typename S>
 __global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__ flags,
-                               long long stride, int naddr, float factor) {
+                               Tiling t, int naddr, float factor) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < naddr;
        c += (long long)gridDim.x * blockDim.x) {
     if (flags[c] & kSolid) continue;
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
-      S* q = buf + k * stride + c;
+      S* q = buf + t.slot(k, c);
       *q = Storage<S>::from_float(Storage<S>::to_float(*q) * factor);
     }
   }

@@ -28,7 +28,7 @@ struct lbm_domain_s {
   Geometry geo;
   std::string err;
   // derived
-  long long stride = 0;  // elements per direction plane
+  long long state_elems = 0;  // elements of one state buffer (19 per address, whole runs)
   size_t elem = 0;       // bytes per stored population
   Tiling tiling{};       // tiled cell order of the device buffers
   long long naddr = 0;   // device cell addresses (cells plus tile padding)
@@ -129,10 +129,6 @@ double pick_sigma(double m) {
   return std::ldexp(1.0, (int)std::floor(std::log2(kScaleTarget / m)));
 }
 
-// Direction planes are padded so that the 19 streams do not start on the same
-// HBM channel: round the cell count up to 1024 elements, plus 512 elements.
-long long plane_stride(int64_t ncell) { return (long long)(((ncell + 1023) / 1024) * 1024 + 512); }
-
 // Tiles of 64 cells, 2^tw_log2 wide.  Compact tiles for states beyond the
 // last-level cache (512^3 sphere pack, FP32 CLI: 16 x 4 tiles 2.51 ms per
 // step against 2.56 ms for 8 x 8 tiles and 2.98 ms for rows); 64 x 1 tiles
@@ -188,7 +184,10 @@ void layout(lbm_domain d) {
   d->cell_addrs = (long long)d->tiling.plane * d->geo.nz_cell;
   d->naddr = (long long)d->tiling.plane * d->geo.nz;
   const int64_t n = d->naddr;
-  d->stride = plane_stride(n);
+  // state runs: one tile, or the two tiles of a two-cell wavefront
+  d->tiling.run_log2 = d->pairs ? 7 : 6;
+  const long long run = 1LL << d->tiling.run_log2;
+  d->state_elems = (long long)kQ * ((n + run - 1) / run * run);
   // 8 wavefronts (16 x 4 tiles: 128 x 4 cells) with compact tiles, 2 with
   // two cells per lane (32 x 8 cells), 4 (256 cells of a row) with rows;
   // never more than a plane has work for
@@ -199,7 +198,7 @@ void layout(lbm_domain d) {
   while (d->waves > d->rows && d->waves / d->rows > units) d->waves /= 2;
   static_assert(16 * 64 <= kStepThreads, "step workgroups exceed the kernel's launch bound");
   size_t o = 0;
-  const size_t bufb = align256((size_t)kQ * d->stride * d->elem);
+  const size_t bufb = align256((size_t)d->state_elems * d->elem);
   d->off_buf[0] = o;
   o += bufb;
   d->off_buf[1] = o;
@@ -261,7 +260,6 @@ StepParams step_params(lbm_domain d) {
   sp.nx = d->geo.nx;
   sp.ny = d->geo.ny;
   sp.nz = d->geo.nz;
-  sp.stride = d->stride;
   sp.jump_axis = (1.0 / 18.0) * d->p.delta_rho;
   sp.jump_diag = (1.0 / 36.0) * d->p.delta_rho;
   sp.omega_p = d->omega_p;
@@ -544,8 +542,7 @@ lbm_status upload_cell_params(lbm_domain d) {
     sp.nx = d->geo.nx;
     sp.ny = d->geo.ny;
     sp.nz = d->geo.nz_cell;
-    sp.stride = d->stride;
-    sp.jump_axis = (1.0 / 18.0) * c.delta_rho;
+      sp.jump_axis = (1.0 / 18.0) * c.delta_rho;
     sp.jump_diag = (1.0 / 36.0) * c.delta_rho;
     sp.omega_p = 1.0 / c.tau;
     sp.omega_m = d->p.collision == LBM_TRT ? 1.0 / (0.5 + c.magic / (c.tau - 0.5)) : sp.omega_p;
@@ -599,11 +596,11 @@ lbm_status batch_run(lbm_domain d, double tol, int64_t max_steps, int64_t* steps
   if (d->p.storage == LBM_FP64)
     batch_align_kernel<double><<<2048, 256, 0, d->stream>>>(
         (double*)d->buf[d->cur], (const double*)d->buf[1 - d->cur], d->d_status, d->cur,
-        d->cell_addrs, d->stride, d->batch);
+        d->cell_addrs, d->tiling, d->batch);
   else
     batch_align_kernel<float><<<2048, 256, 0, d->stream>>>(
         (float*)d->buf[d->cur], (const float*)d->buf[1 - d->cur], d->d_status, d->cur,
-        d->cell_addrs, d->stride, d->batch);
+        d->cell_addrs, d->tiling, d->batch);
   HIP_OK(d, hipGetLastError());
   d->status_host.resize(d->batch);
   HIP_OK(d, hipMemcpyAsync(d->status_host.data(), d->d_status, d->batch * sizeof(CellStatus),
@@ -658,7 +655,7 @@ lbm_status reduce_state_into(lbm_domain d, double* partials, double* result, dou
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     reduce_state_kernel<S><<<kRedBlocks, kRedThreads, 0, d->stream>>>(
-        (const S*)d->buf[d->cur], d->flags, d->stride, naddr, d->sigma, partials);
+        (const S*)d->buf[d->cur], d->flags, d->tiling, naddr, d->sigma, partials);
     return 0;
   });
   reduce_final_kernel<<<1, kRedThreads, 0, d->stream>>>(partials, kRedBlocks, 1 << 4, result);
@@ -684,7 +681,7 @@ lbm_status adjust_scale(lbm_domain d, double m) {
   const float factor = (float)(ns / d->sigma);
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
-    rescale_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[d->cur], d->flags, d->stride,
+    rescale_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[d->cur], d->flags, d->tiling,
                                                    (int)d->naddr, factor);
     return 0;
   });
@@ -806,7 +803,7 @@ LBM_API lbm_status lbm_get_info(lbm_domain d, lbm_info* info) {
   info->n_links = (int64_t)d->geo.link_cell.size();
   info->n_fallback = d->geo.n_fallback;
   info->workspace_bytes = (int64_t)d->total;
-  info->plane_stride = d->stride;
+  info->state_elems = d->state_elems;
   info->nu = d->nu;
   info->omega_plus = d->omega_p;
   info->omega_minus = d->omega_m;
@@ -912,7 +909,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     const int xs = (x + kLat.ex[j] + nx) % nx, ys = (y + kLat.ey[j] + ny) % ny,
               zs = (z - z0 + kLat.ez[j] + zc) % zc;
     const int64_t s = (int64_t)(z0 / zc) * d->cell_addrs + d->tiling.at(xs, ys, zs);
-    slot[i] = (long long)kLat.opp[j] * d->stride + s;
+    slot[i] = d->tiling.slot(kLat.opp[j], s);
     const double q = d->geo.link_q[i];
     // eq. (CLI): a = (1 - 2q)/(1 + 2q); links without a second fluid node
     // fall back to simple bounce-back (a = 0).  The other interpolated
@@ -928,7 +925,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
     HIP_OK(d, hipMemcpyAsync(d->link_slot, slot.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
     HIP_OK(d, hipMemcpyAsync(d->link_coef, coef.data(), nl * 8, hipMemcpyHostToDevice, d->stream));
   }
-  const long long nel = (long long)kQ * d->stride;
+  const long long nel = d->state_elems;
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     fill_kernel<S><<<2048, 256, 0, d->stream>>>((S*)d->buf[0], nel);
@@ -975,7 +972,7 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const
     with_storage(d->p.storage, [&](auto tag) {
       using S = decltype(tag);
       init_eq_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-          (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, (int)c0, cnt,
+          (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->sigma, (int)c0, cnt,
           d->stage);
       return 0;
     });
@@ -998,7 +995,6 @@ LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
   choose_sigma(d, m);
   const size_t chunk = d->stage_cells * 4;
   for (int k = 0; k < kQ; ++k) {
-    char* plane = (char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
     for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
       const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
       HIP_OK(d, hipMemcpyAsync(d->stage, g + (size_t)k * n + c0, (size_t)cnt * 8,
@@ -1006,7 +1002,7 @@ LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
       with_storage(d->p.storage, [&](auto tag) {
         using S = decltype(tag);
         set_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-            (S*)plane, d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
+            (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
         return 0;
       });
       HIP_OK(d, hipGetLastError());
@@ -1024,13 +1020,12 @@ LBM_API lbm_status lbm_get_state(lbm_domain d, double* g) {
   const int64_t n = d->geo.ncell;
   const size_t chunk = d->stage_cells * 4;
   for (int k = 0; k < kQ; ++k) {
-    const char* plane = (const char*)d->buf[d->cur] + (size_t)k * d->stride * d->elem;
     for (int64_t c0 = 0; c0 < n; c0 += (int64_t)chunk) {
       const int cnt = (int)std::min<int64_t>((int64_t)chunk, n - c0);
       with_storage(d->p.storage, [&](auto tag) {
         using S = decltype(tag);
         get_plane_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-            (const S*)plane, d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
+            (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, k, d->sigma, (int)c0, cnt, d->stage);
         return 0;
       });
       HIP_OK(d, hipGetLastError());
@@ -1111,7 +1106,7 @@ LBM_API lbm_status lbm_macroscopic(lbm_domain d, double* drho, double* u) {
     with_storage(d->p.storage, [&](auto tag) {
       using S = decltype(tag);
       macro_kernel<S><<<(cnt + 255) / 256, 256, 0, d->stream>>>(
-          (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, (int)c0, cnt,
+          (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->sigma, (int)c0, cnt,
           d->stage);
       return 0;
     });
@@ -1139,7 +1134,7 @@ LBM_API lbm_status lbm_macroscopic_device(lbm_domain d, double* fields) {
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     macro_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
-        (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, 0, n, fields);
+        (const S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->sigma, 0, n, fields);
     return 0;
   });
   HIP_OK(d, hipGetLastError());
@@ -1158,7 +1153,7 @@ LBM_API lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* field
   with_storage(d->p.storage, [&](auto tag) {
     using S = decltype(tag);
     init_eq_kernel<S><<<(n + 255) / 256, 256, 0, d->stream>>>(
-        (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->stride, d->sigma, 0, n, fields);
+        (S*)d->buf[d->cur], d->flags, d->tiling, cell_cells(d), (int)d->cell_addrs, d->sigma, 0, n, fields);
     return 0;
   });
   HIP_OK(d, hipGetLastError());

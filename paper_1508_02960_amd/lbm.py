@@ -67,7 +67,7 @@ class CellParams(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_fluid", C.c_int64), ("n_links", C.c_int64),
                 ("n_fallback", C.c_int64), ("workspace_bytes", C.c_int64),
-                ("plane_stride", C.c_int64), ("nu", C.c_double), ("omega_plus", C.c_double),
+                ("state_elems", C.c_int64), ("nu", C.c_double), ("omega_plus", C.c_double),
                 ("omega_minus", C.c_double), ("bytes_per_fluid_update", C.c_int64),
                 ("storage_scale", C.c_double), ("tile_width", C.c_int32),
                 ("tile_height", C.c_int32)]

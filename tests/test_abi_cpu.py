@@ -142,8 +142,8 @@ def test_info_and_workspace_size():
                    wall="cli")
     info = d.info
     assert info.n_cells == 16 * 12 * 20
-    assert info.plane_stride >= info.n_cells
-    assert info.workspace_bytes >= 2 * 19 * info.plane_stride * 4 + 4 * info.n_cells
+    assert info.state_elems >= 19 * info.n_cells
+    assert info.workspace_bytes >= 2 * info.state_elems * 4 + 4 * info.n_cells
     assert info.bytes_per_fluid_update == 152
     assert abs(info.nu - 0.1) < 1e-15 and abs(info.omega_plus - 1.25) < 1e-15
     d64 = lbm.Domain(shape, tau=0.8, spheres=inputs.centred_sphere(shape, 9.0), bind=False,
