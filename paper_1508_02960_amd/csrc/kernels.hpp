@@ -3,7 +3,8 @@
 // Data layout in HBM: two population buffers (A: current post-collision
 // state, B: next) of g_k = f_k - w_k, 19 values per cell address, stored in
 // runs (Tiling::slot): a run of 64 or 128 consecutive addresses holds its 19
-// directions one after the other.  Cells are stored in tiled order
+// directions one after the other (FP32, FP64), or the whole state is 19
+// padded direction planes (16-bit values).  Cells are stored in tiled order
 // (Tiling): each z plane is cut into tiles of 64 cells, one wavefront each.
 // States well beyond the last-level cache use compact tiles (16 x 4, or
 // 32 x 2 for 16-bit values), so a 128-byte line covers a compact patch of
@@ -52,7 +53,8 @@ struct Tiling {
   int ntx;               // tiles per tile row (padded nx / tile width)
   int nty;               // tile rows per plane
   int plane;             // cells per z plane including padding: ntx * nty * 64
-  int run_log2;          // state buffers: runs of 2^run_log2 consecutive addresses
+  int run_log2;          // state buffers: runs of 2^run_log2 consecutive addresses,
+  long long run_pitch;   // ... each direction of a run run_pitch elements after the last
   __host__ __device__ int xpart(int x) const {
     return ((x >> tw_log2) << 6) | (x & ((1 << tw_log2) - 1));
   }
@@ -69,12 +71,13 @@ struct Tiling {
     y = ((t / ntx) << th_log2) + (l >> tw_log2);
   }
   // Index of direction k of the cell at address a in a state buffer.  The
-  // addresses are cut into runs of 2^run_log2 (one tile, or the two tiles of
-  // a two-cell wavefront) and each run stores its 19 directions one after
-  // the other, so a wavefront's load or store of one direction is one
-  // contiguous run and all 19 lie within 19 runs of each other.
+  // addresses are cut into runs of 2^run_log2 and each run stores its 19
+  // directions one after the other, run_pitch apart: with short runs (two
+  // tiles, run_pitch = 2^run_log2) a wavefront's 19 loads or stores lie close
+  // together; with one run holding all addresses (run_pitch the padded
+  // address count) the state is 19 direction planes.
   __host__ __device__ long long slot(int k, long long a) const {
-    return ((((a >> run_log2) * kQ) + k) << run_log2) + (a & ((1LL << run_log2) - 1));
+    return ((a >> run_log2) * kQ + k) * run_pitch + (a & ((1LL << run_log2) - 1));
   }
   // address of the cell with row-major index c = x + nx (y + ny z)
   __host__ __device__ int from_linear(long long c) const {
@@ -83,6 +86,28 @@ struct Tiling {
     return at(x, (int)(r % ny), (int)(r / ny));
   }
 };
+
+// Tiling::slot for a kernel's storage type, with the layout fixed at compile
+// time (16-bit values: direction planes, k * run_pitch + a; FP32 and FP64:
+// runs of 2^run_log2 addresses), so that the per-lane address is the cell
+// address plus a wavefront-uniform offset where it can be.
+template <typename S>
+__device__ __forceinline__ long long state_slot(const Tiling& t, int k, long long a) {
+  if constexpr (sizeof(S) == 2)
+    return k * t.run_pitch + a;
+  else
+    return ((((a >> t.run_log2) * kQ) + k) << t.run_log2) + (a & ((1LL << t.run_log2) - 1));
+}
+
+// Element of direction k of the cell at address a: for direction planes the
+// plane's base (wavefront-uniform) plus the 32-bit address.
+template <typename S, typename P>
+__device__ __forceinline__ P* state_ptr(P* base, const Tiling& t, int k, int a) {
+  if constexpr (sizeof(S) == 2)
+    return (base + k * t.run_pitch) + a;
+  else
+    return base + state_slot<S>(t, k, a);
+}
 
 // Cell classes (one byte per cell, tiled order).
 constexpr uint8_t kClsSolid = 1;  // solid (or padding) cell
@@ -512,7 +537,7 @@ __device__ __forceinline__ FarNode far_node(const StepParams& p, int x, int y, i
 template <typename S, typename C>
 __device__ __forceinline__ C far_value(const S* __restrict__ src, const StepParams& p, FarNode f,
                                        int kk) {
-  C v = (C)Storage<S>::to_float(src[p.t.slot(kk, f.c)]);
+  C v = (C)Storage<S>::to_float(src[state_slot<S>(p.t, kk, f.c)]);
   const C jw = (C)(wclass(kk) == 1 ? p.jump_axis : p.jump_diag);
   if (f.cross > 0) v -= jw;
   if (f.cross < 0) v += jw;
@@ -528,7 +553,7 @@ __device__ __forceinline__ void stored_moments(const S* __restrict__ src, const 
   u[0] = u[1] = u[2] = (C)0;
 #pragma unroll
   for (int kk = 0; kk < kQ; ++kk) {
-    const C v = (C)Storage<S>::to_float(src[t.slot(kk, c)]);
+    const C v = (C)Storage<S>::to_float(src[state_slot<S>(t, kk, c)]);
     drho += v;
     u[0] += (C)kLat.ex[kk] * v;
     u[1] += (C)kLat.ey[kk] * v;
@@ -760,7 +785,7 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
   // pull: direction k arrives from x - e_k (raw stored values)
 #pragma unroll
   for (int k = 0; k < kQ; ++k)
-    g[k] = (C)St::to_float(src[p.t.slot(k, n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k]))]);
+    g[k] = (C)St::to_float(*state_ptr<S>(src, p.t, k, n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])));
 
   // wall links: the pulled raw value is the stored coefficient a (CLI) or
   // the wall distance q (general rules)
@@ -772,11 +797,11 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
     // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
     // come from the same values.
 #pragma unroll
-    for (int k = 1; k < kQ; ++k) own[k] = src[p.t.slot(k, c)];
+    for (int k = 1; k < kQ; ++k) own[k] = *state_ptr<S>(src, p.t, k, c);
     if constexpr (WALL == kGEN) {
       C m1[4] = {(C)0, (C)0, (C)0, (C)0};
       if (p.wall == kRuleIEBB) {
-        own[0] = src[p.t.slot(0, c)];
+        own[0] = src[state_slot<S>(p.t, 0, c)];
 #pragma unroll
         for (int kk = 0; kk < kQ; ++kk) {
           const C v = (C)St::to_float(own[kk]);
@@ -816,7 +841,7 @@ __device__ __forceinline__ void solid_node(const S* __restrict__ src, S (&out)[k
   out[0] = Storage<S>::from_float(0);
 #pragma unroll
   for (int k = 1; k < kQ; ++k)
-    out[k] = (fl & (1u << k)) ? src[t.slot(k, c)] : Storage<S>::from_float(0);
+    out[k] = (fl & (1u << k)) ? src[state_slot<S>(t, k, c)] : Storage<S>::from_float(0);
 }
 
 // Whether this lane stores, given the fluid lanes of its wavefront: fluid
@@ -854,9 +879,9 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[k
 #pragma unroll
   for (int k = 0; k < kQ; ++k) {
     if constexpr (NT)
-      nontemporal_store(out[k], &dst[t.slot(k, c)]);
+      nontemporal_store(out[k], state_ptr<S>(dst, t, k, c));
     else
-      dst[t.slot(k, c)] = out[k];
+      *state_ptr<S>(dst, t, k, c) = out[k];
   }
 }
 
@@ -1065,10 +1090,13 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
     for (int k = 0; k < kQ; ++k) {
       const int ex = kLat.ex[k];
       const int row = ys[1 - kLat.ey[k]] + zs[1 - kLat.ez[k]];
+      // 16-bit states are direction planes: plane k's words, indexed by half
+      // the (even) cell address
+      const uint32_t* sk = s32 + (state_slot<S>(t, k, 0) >> 1);
       const int a0 = row_reads ? xs_0 + row : 0;
-      raw[k] = s32[t.slot(k, a0) >> 1];
-      if (ex == 1) edge[k] = s32[t.slot(k, row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
-      if (ex == -1) edge[k] = s32[t.slot(k, row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
+      raw[k] = sk[a0 >> 1];
+      if (ex == 1) edge[k] = sk[(row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
+      if (ex == -1) edge[k] = sk[(row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
     }
     // Boundary pairs: both flag words and the pair's own words, requested
     // with the pulls (one memory round trip): wall rules of link cells, and
@@ -1080,7 +1108,7 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
     if (links) {
       flw = *reinterpret_cast<const uint2*>(flags + c);
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) own_w[k] = s32[t.slot(k, c) >> 1];
+      for (int k = 0; k < kQ; ++k) own_w[k] = s32[(state_slot<S>(t, k, 0) >> 1) + (c >> 1)];
     }
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
@@ -1147,7 +1175,7 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
         uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
-          uint32_t* q = d32 + (t.slot(k, c) >> 1);
+          uint32_t* q = d32 + (state_slot<S>(t, k, 0) >> 1) + (c >> 1);
           if constexpr (NT)
             __builtin_nontemporal_store(outw[k], q);
           else
@@ -1343,7 +1371,7 @@ __global__ void batch_align_kernel(S* __restrict__ to, const S* __restrict__ fro
     const int b = (int)(i / cell_size);
     if (st[b].status == 0 || st[b].parity == to_parity) continue;
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) to[t.slot(k, i)] = from[t.slot(k, i)];
+    for (int k = 0; k < kQ; ++k) to[state_slot<S>(t, k, i)] = from[state_slot<S>(t, k, i)];
   }
 }
 
@@ -1377,7 +1405,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_state_kernel(const S* __re
     if (flags[c] & kSolid) continue;
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(src[t.slot(k, c)], k, sigma);
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(src[state_slot<S>(t, k, c)], k, sigma);
     double rho, ux, uy, uz;
     moments<double>(g, rho, ux, uy, uz);
     const double u2 = ux * ux + uy * uy + uz * uz;
@@ -1424,29 +1452,29 @@ __global__ __launch_bounds__(kRedThreads) void drag_kernel(const S* __restrict__
     for (int k = 1; k < kQ; ++k) {
       if (!(fl & (1u << k))) continue;
       const int j = kLat.opp[k];
-      const double own_j = stored_to_g<S>(src[p.t.slot(j, c)], j, p.sigma);
+      const double own_j = stored_to_g<S>(src[state_slot<S>(p.t, j, c)], j, p.sigma);
       double back = own_j;
       if constexpr (WALL == kGEN) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double q = (double)Storage<S>::to_float(src[p.t.slot(k, p.t.at(sx, sy, sz))]);
+        const double q = (double)Storage<S>::to_float(src[state_slot<S>(p.t, k, p.t.at(sx, sy, sz))]);
         const FarNode n2 = far_node(p, x, y, z, k, 1);
         back = general_wall_value<S, double>(src, flags, p, x, y, z, c, k, q, fl, m1,
-                                             (double)Storage<S>::to_float(src[p.t.slot(j, n2.c)]),
-                                             (double)Storage<S>::to_float(src[p.t.slot(j, c)]),
-                                             (double)Storage<S>::to_float(src[p.t.slot(k, c)]));
+                                             (double)Storage<S>::to_float(src[state_slot<S>(p.t, j, n2.c)]),
+                                             (double)Storage<S>::to_float(src[state_slot<S>(p.t, j, c)]),
+                                             (double)Storage<S>::to_float(src[state_slot<S>(p.t, k, c)]));
       } else if (WALL == kCLI) {
         const int sx = (x - kLat.ex[k] + p.nx) % p.nx, sy = (y - kLat.ey[k] + p.ny) % p.ny,
                   sz = (z - kLat.ez[k] + p.nz) % p.nz;
-        const double a = (double)Storage<S>::to_float(src[p.t.slot(k, p.t.at(sx, sy, sz))]);
+        const double a = (double)Storage<S>::to_float(src[state_slot<S>(p.t, k, p.t.at(sx, sy, sz))]);
         const int tx = x + kLat.ex[k];
         const int fx = (tx + p.nx) % p.nx, fy = (y + kLat.ey[k] + p.ny) % p.ny,
                   fz = (z + kLat.ez[k] + p.nz) % p.nz;
-        double far_j = stored_to_g<S>(src[p.t.slot(j, p.t.at(fx, fy, fz))], j, p.sigma);
+        double far_j = stored_to_g<S>(src[state_slot<S>(p.t, j, p.t.at(fx, fy, fz))], j, p.sigma);
         const double jw = kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag;
         if (tx >= p.nx) far_j -= jw;
         if (tx < 0) far_j += jw;
-        back = a * far_j - a * stored_to_g<S>(src[p.t.slot(k, c)], k, p.sigma) + own_j;
+        back = a * far_j - a * stored_to_g<S>(src[state_slot<S>(p.t, k, c)], k, p.sigma) + own_j;
       }
       const double tot = (own_j + kLat.w[j]) + (back + kLat.w[k]);
       v[0] += kLat.ex[j] * tot;
@@ -1515,7 +1543,7 @@ __global__ void get_plane_kernel(const S* __restrict__ buf, const uint32_t* __re
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
-  out[i] = (flags[a] & kSolid) ? 0.0 : stored_to_g<S>(buf[t.slot(k, a)], k, sigma);
+  out[i] = (flags[a] & kSolid) ? 0.0 : stored_to_g<S>(buf[state_slot<S>(t, k, a)], k, sigma);
 }
 
 template <typename S>
@@ -1525,7 +1553,7 @@ __global__ void set_plane_kernel(S* __restrict__ buf, const uint32_t* __restrict
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = addr_of(t, c0 + i, cell_cells, cell_addrs);
-  if (!(flags[a] & kSolid)) buf[t.slot(k, a)] = g_to_stored<S>(in[i], k, sigma);
+  if (!(flags[a] & kSolid)) buf[state_slot<S>(t, k, a)] = g_to_stored<S>(in[i], k, sigma);
 }
 
 // g = g^eq(drho, u) for fluid cells [c0, c0 + n) (row-major order); stage =
@@ -1551,7 +1579,7 @@ __global__ void init_eq_kernel(S* __restrict__ buf, const uint32_t* __restrict__
   LBM_EQ(17) LBM_EQ(18)
 #undef LBM_EQ
 #pragma unroll
-  for (int k = 0; k < kQ; ++k) buf[t.slot(k, c)] = g_to_stored<S>((double)g[k], k, sigma);
+  for (int k = 0; k < kQ; ++k) buf[state_slot<S>(t, k, c)] = g_to_stored<S>((double)g[k], k, sigma);
 }
 
 // drho, u of cells [c0, c0 + n) (row-major order) into stage (drho | ux |
@@ -1567,7 +1595,7 @@ __global__ void macro_kernel(const S* __restrict__ buf, const uint32_t* __restri
   if (!(flags[c] & kSolid)) {
     double g[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(buf[t.slot(k, c)], k, sigma);
+    for (int k = 0; k < kQ; ++k) g[k] = stored_to_g<S>(buf[state_slot<S>(t, k, c)], k, sigma);
     moments<double>(g, rho, ux, uy, uz);
   }
   stage[i] = rho;
@@ -1586,7 +1614,7 @@ __global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__
     if (flags[c] & kSolid) continue;
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
-      S* q = buf + t.slot(k, c);
+      S* q = buf + state_slot<S>(t, k, c);
       *q = Storage<S>::from_float(Storage<S>::to_float(*q) * factor);
     }
   }

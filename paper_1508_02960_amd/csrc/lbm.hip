@@ -184,10 +184,22 @@ void layout(lbm_domain d) {
   d->cell_addrs = (long long)d->tiling.plane * d->geo.nz_cell;
   d->naddr = (long long)d->tiling.plane * d->geo.nz;
   const int64_t n = d->naddr;
-  // state runs: one tile, or the two tiles of a two-cell wavefront
-  d->tiling.run_log2 = d->pairs ? 7 : 6;
-  const long long run = 1LL << d->tiling.run_log2;
-  d->state_elems = (long long)kQ * ((n + run - 1) / run * run);
+  // State runs (Tiling::slot).  512^3 sphere pack, ms per step: FP32 in
+  // runs of 128 addresses 2.37, of 64 2.40, of 256 2.40, in direction
+  // planes 2.50; FP16 (two cells per lane) in planes 1.65, in runs of 128
+  // to 4096 addresses 1.80-1.83.  Batch cells start on a run (runs of 64).
+  if (d->elem == 2 && !d->batch) {
+    d->tiling.run_log2 = 40;  // one run: direction planes
+    // planes padded so that the 19 streams do not start on the same HBM
+    // channel: the address count rounded up to 1024, plus 512
+    d->tiling.run_pitch = ((n + 1023) / 1024) * 1024 + 512;
+    d->state_elems = (long long)kQ * d->tiling.run_pitch;
+  } else {
+    d->tiling.run_log2 = d->batch ? 6 : 7;
+    d->tiling.run_pitch = 1LL << d->tiling.run_log2;
+    const long long run = d->tiling.run_pitch;
+    d->state_elems = (long long)kQ * ((n + run - 1) / run * run);
+  }
   // 8 wavefronts (16 x 4 tiles: 128 x 4 cells) with compact tiles, 2 with
   // two cells per lane (32 x 8 cells), 4 (256 cells of a row) with rows;
   // never more than a plane has work for
