@@ -112,6 +112,7 @@ __device__ __forceinline__ P* state_ptr(P* base, const Tiling& t, int k, int a) 
 // Cell classes (one byte per cell, tiled order).
 constexpr uint8_t kClsSolid = 1;  // solid (or padding) cell
 constexpr uint8_t kClsLinks = 2;  // the cell's flag word has link bits
+constexpr uint8_t kClsNearWall = 4;  // x_f2 of a wall link (IEBB reads its velocity)
 
 struct StepParams {
   Tiling t;
@@ -130,6 +131,12 @@ struct StepParams {
   // or two x-adjacent tiles with two cells per lane) of bh consecutive tile
   // rows; nbx workgroups span a band of bh tile rows
   int bw, bh, nbx;
+  // IEBB, one domain: the velocity (momentum j, as stored_moments) of the
+  // cells marked kClsNearWall, 4 values of the compute type per address;
+  // side_in belongs to the step's source state, side_out to the state it
+  // writes (null: IEBB sums the 19 stored values at x_f2 instead)
+  void* side_in;
+  void* side_out;
 };
 
 // ------------------------------------------------------------ storage types
@@ -624,8 +631,16 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
       const C tau = (C)(1.0 / p.omega_p);
       if (q < (C)0.5) {
         if (!f2) return own_j;
-        C d2;
-        stored_moments<S, C>(src, p.t, n2.c, d2, ubf);
+        if (p.side_in) {
+          // written for x_f2 by the step that produced the source state
+          const C* u2 = static_cast<const C*>(p.side_in) + 4LL * n2.c;
+          ubf[0] = u2[0];
+          ubf[1] = u2[1];
+          ubf[2] = u2[2];
+        } else {
+          C d2;
+          stored_moments<S, C>(src, p.t, n2.c, d2, ubf);
+        }
         X = (two * q - one) / (tau - two);
       } else {
         const C f = one - (C)3 / (two * q);
@@ -885,6 +900,19 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[k
   }
 }
 
+// IEBB's side buffer: a near-wall cell's velocity (the pre-collision
+// momentum, which the collision conserves, i.e. that of the state written).
+template <typename C>
+__device__ __forceinline__ void store_side(const StepParams& p, uint8_t cls, int c,
+                                           const C (&mom)[5]) {
+  if (p.side_out && (cls & kClsNearWall)) {
+    C* u = static_cast<C*>(p.side_out) + 4LL * c;
+    u[0] = mom[1];
+    u[1] = mom[2];
+    u[2] = mom[3];
+  }
+}
+
 // Cell of this thread in plane z: wavefront threadIdx.y of the block takes
 // tile blockIdx.x * blockDim.y + threadIdx.y of the plane (tiles in row-major
 // order), lane threadIdx.x its cell in the tile, so the lanes of a wavefront
@@ -962,6 +990,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
     C mom[5];
     update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
     store_node<S, NT>(dst, out, p.t, tc.c);
+    if constexpr (WALL == kGEN) store_side<C>(p, k, tc.c, mom);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (!(k & kClsSolid)) {
@@ -970,6 +999,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
       C mom[5];
       update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
       store_node<S, NT>(dst, out, p.t, tc.c);
+      if constexpr (WALL == kGEN) store_side<C>(p, k, tc.c, mom);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
       v[0] = ux;
@@ -1617,6 +1647,24 @@ __global__ void rescale_kernel(S* __restrict__ buf, const uint32_t* __restrict__
       S* q = buf + state_slot<S>(t, k, c);
       *q = Storage<S>::from_float(Storage<S>::to_float(*q) * factor);
     }
+  }
+}
+
+// IEBB's side buffer for a state set from outside the time loop: the
+// velocity of every near-wall cell from its stored values.
+template <typename S>
+__global__ void side_moments_kernel(const S* __restrict__ buf, const uint8_t* __restrict__ cls,
+                                    Tiling t, int naddr, void* side) {
+  using C = typename ComputeOf<S>::type;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < naddr;
+       c += (long long)gridDim.x * blockDim.x) {
+    if ((cls[c] & (kClsNearWall | kClsSolid)) != kClsNearWall) continue;
+    C d, u[3];
+    stored_moments<S, C>(buf, t, (int)c, d, u);
+    C* o = static_cast<C*>(side) + 4 * c;
+    o[0] = u[0];
+    o[1] = u[1];
+    o[2] = u[2];
   }
 }
 

@@ -50,7 +50,8 @@ struct lbm_domain_s {
   void* buf[2] = {nullptr, nullptr};
   int cur = 0;  // buf[cur] holds the current state
   uint32_t* flags = nullptr;
-  uint8_t* cls = nullptr;  // class byte per cell (kClsSolid, kClsLinks)
+  uint8_t* cls = nullptr;  // class byte per cell (kClsSolid, kClsLinks, kClsNearWall)
+  void* side[2] = {nullptr, nullptr};  // IEBB: near-wall velocities of buf[0], buf[1]
   long long* link_slot = nullptr;
   double* link_coef = nullptr;
   double* partials = nullptr;   // per-block partial sums
@@ -78,7 +79,8 @@ struct lbm_domain_s {
   // layout offsets
   size_t off_buf[2] = {0, 0}, off_flags = 0, off_cls = 0, off_slot = 0, off_coef = 0, off_part = 0,
          off_part2 = 0, off_res = 0, off_stage = 0, off_cells = 0, off_active = 0,
-         off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, total = 0;
+         off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, off_side[2] = {0, 0},
+         side_bytes = 0, total = 0;
 };
 
 namespace {
@@ -166,6 +168,11 @@ dim3 step_grid(lbm_domain d) {
 // 256 MB last-level cache (measured: 15% faster at 256^3 FP32, 2.5 GB;
 // 1.6% slower at 128^3, 0.32 GB, where much of the state stays cached).
 constexpr size_t kStreamingBytes = size_t(1) << 30;
+
+// IEBB on one domain keeps the velocity of the cells next to its wall links
+// in a side buffer per state (StepParams::side_in / side_out); batches sum
+// the stored values instead.
+bool uses_side(lbm_domain d) { return d->p.wall == LBM_WALL_IEBB && !d->batch; }
 
 void layout(lbm_domain d) {
   d->elem = storage_bytes(d->p.storage);
@@ -260,6 +267,12 @@ void layout(lbm_domain d) {
   o += align256(nb * kRedVals * sizeof(double));
   d->off_nactive = o;
   o += align256(sizeof(int));
+  // IEBB on one domain: 4 values of the compute type per address and state
+  d->side_bytes = uses_side(d) ? (size_t)n * 4 * (d->elem == 8 ? 8 : 4) : 0;
+  for (int i = 0; i < 2; ++i) {
+    d->off_side[i] = o;
+    o += align256(d->side_bytes);
+  }
   d->total = o;
 }
 
@@ -281,6 +294,8 @@ StepParams step_params(lbm_domain d) {
   sp.sigma = d->sigma;
   sp.wall = d->p.wall;
   sp.solid_writes = d->solid_writes;
+  sp.side_in = d->side[d->cur];
+  sp.side_out = d->side[1 - d->cur];
   sp.bw = std::max(1, d->waves / std::max(1, d->rows));
   sp.bh = std::max(1, d->rows);
   sp.nbx = d->batch ? 1 : step_nbx(d);
@@ -343,6 +358,8 @@ lbm_status build_graph(lbm_domain d, int from) {
   for (int i = 0; i < kGraphSteps; ++i) {
     const void* src = d->buf[(from + i) & 1];
     void* dst = d->buf[(from + i + 1) & 1];
+    sp.side_in = d->side[(from + i) & 1];
+    sp.side_out = d->side[(from + i + 1) & 1];
     void* args[] = {(void*)&src, (void*)&dst, (void*)&cl, (void*)&fl, (void*)&sp, (void*)&part};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
@@ -677,6 +694,22 @@ lbm_status reduce_state_into(lbm_domain d, double* partials, double* result, dou
   return LBM_OK;
 }
 
+// IEBB's side buffer of the current state, from its stored values (after
+// the state was set from outside the time loop).
+lbm_status refresh_side(lbm_domain d) {
+  if (!d->side[d->cur]) return LBM_OK;
+  with_storage(d->p.storage, [&](auto tag) {
+    using S = decltype(tag);
+    if constexpr (kUnscaledStorage<S>)
+      side_moments_kernel<S><<<2048, 256, 0, d->stream>>>((const S*)d->buf[d->cur], d->cls,
+                                                          d->tiling, (int)d->naddr,
+                                                          d->side[d->cur]);
+    return 0;
+  });
+  HIP_OK(d, hipGetLastError());
+  return LBM_OK;
+}
+
 lbm_status reduce_state(lbm_domain d, double* vals) {
   return reduce_state_into(d, d->partials, d->result, vals);
 }
@@ -880,6 +913,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->d_status = (CellStatus*)(d->ws + d->off_status);
   d->d_results = (double*)(d->ws + d->off_results);
   d->d_nactive = (int*)(d->ws + d->off_nactive);
+  for (int i = 0; i < 2; ++i) d->side[i] = d->side_bytes ? d->ws + d->off_side[i] : nullptr;
   if (d->batch) {
     lbm_status bst = upload_cell_params(d);
     if (bst != LBM_OK) return bst;
@@ -900,6 +934,19 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
       const uint32_t w = d->geo.flags[(size_t)c];
       fl[(size_t)a] = w;
       cl[(size_t)a] = (uint8_t)(((w & kSolid) ? kClsSolid : 0) | ((w & kLinkMask) ? kClsLinks : 0));
+    }
+    if (uses_side(d)) {
+      // x_f2 = x + e_k of every link k at x (the link's wall is at x - e_k)
+      const int nx = d->geo.nx, ny = d->geo.ny, nz = d->geo.nz;
+      for (size_t i = 0; i < d->geo.link_cell.size(); ++i) {
+        const int64_t c = d->geo.link_cell[i];
+        const int j = d->geo.link_dir[i];  // direction from the fluid node to the wall
+        const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+        const int fx = (x - kLat.ex[j] + nx) % nx, fy = (y - kLat.ey[j] + ny) % ny,
+                  fz = (z - kLat.ez[j] + nz) % nz;
+        const int64_t a = d->tiling.at(fx, fy, fz);
+        if (!(cl[(size_t)a] & kClsSolid)) cl[(size_t)a] |= kClsNearWall;
+      }
     }
     HIP_OK(d, hipMemcpyAsync(d->flags, fl.data(), (size_t)na * 4, hipMemcpyHostToDevice,
                              d->stream));
@@ -952,7 +999,7 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   choose_sigma(d, 0.0);
   d->bound = true;
   d->unstable = false;
-  return LBM_OK;  // buffers are zero: the rest state g = 0
+  return refresh_side(d);  // buffers are zero: the rest state g = 0
 }
 
 // ------------------------------------------------------------------ state
@@ -992,7 +1039,7 @@ LBM_API lbm_status lbm_init_equilibrium(lbm_domain d, const double* drho0, const
     HIP_OK(d, hipStreamSynchronize(d->stream));
   }
   d->unstable = false;
-  return LBM_OK;
+  return refresh_side(d);
 }
 
 LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
@@ -1022,7 +1069,7 @@ LBM_API lbm_status lbm_set_state(lbm_domain d, const double* g) {
     }
   }
   d->unstable = false;
-  return LBM_OK;
+  return refresh_side(d);
 }
 
 LBM_API lbm_status lbm_get_state(lbm_domain d, double* g) {
@@ -1170,7 +1217,7 @@ LBM_API lbm_status lbm_init_equilibrium_device(lbm_domain d, const double* field
   });
   HIP_OK(d, hipGetLastError());
   d->unstable = false;
-  return LBM_OK;
+  return refresh_side(d);
 }
 
 // Outputs of lbm_mean_velocity from the reduced vector.
@@ -1279,7 +1326,9 @@ LBM_API lbm_status lbm_drag(lbm_domain d, double F[3]) {
   if (st != LBM_OK) return st;
   if (d->batch) return fail(d, LBM_ERR_STATE, "per-domain call on a batch; use lbm_batch_results");
   if (!F) return fail(d, LBM_ERR_INVALID_ARG, "F is NULL");
-  const StepParams sp = step_params(d);
+  StepParams sp = step_params(d);
+  // the drag kernel computes in FP64 and sums IEBB's x_f2 values itself
+  sp.side_in = sp.side_out = nullptr;
   const bool cli = d->p.wall == LBM_WALL_CLI;
   const bool gen = wall_template(d->p.wall) == kGEN;
   with_storage(d->p.storage, [&](auto tag) {

@@ -214,6 +214,36 @@ def test_observables_parity(orc, storage, tol, wall):
     d.close()
 
 
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_iebb_near_wall_velocity_through_graphs(orc, storage, tol):
+    """IEBB reads the velocity at x_f2 from the side buffer that the step
+    writing the source state filled; the buffers alternate with the states,
+    also inside the 32-step graphs and the checked steps, and a state set
+    from the host refills them.  70 plain steps (two graph replays and six
+    launches), a new state, 33 more, then 100 steps with checks."""
+    shape = (16, 14, 20)
+    sp = inputs.random_spheres(shape, 4, (2.0, 4.5), seed=61)
+    kw = dict(tau=0.9, magic=0.25, delta_rho=2e-3, collision="trt", wall="iebb", spheres=sp)
+    o, d = _pair(orc, shape, storage=storage, check_interval=25, **kw)
+    u0 = inputs.random_velocity(shape, 5e-3, seed=62)
+    o.init(u0=u0)
+    d.init_equilibrium(u0=u0)
+    fluid = o.mask == 0
+    o.step(70)
+    d.step(70)
+    assert rel(d.get_state(), o.g, fluid) < tol
+    g1 = inputs.random_populations(shape, 1e-3, seed=63)
+    o.set_state(g1)
+    d.set_state(g1)
+    o.step(33)
+    d.step(33)
+    assert rel(d.get_state(), o.g, fluid) < tol
+    d.run_to_residual(0.0, 100)
+    o.step(100)
+    assert rel(d.get_state(), o.g, fluid) < tol
+    d.close()
+
+
 def test_no_solid_exact_acceleration():
     """Without solids U_x(n) = n drho / (3 nx) (pressure jump is the only force)."""
     shape = (5, 6, 9)
