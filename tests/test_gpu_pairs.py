@@ -94,6 +94,31 @@ def test_pair_kernel_large_state_tiles():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("storage,wall", [("fp32", "cli"), ("fp64", "iebb"), ("fp16", "sbb")])
+def test_workgroup_shapes_give_identical_states(storage, wall):
+    """Every workgroup shape (wavefronts across x tile rows, one or two cells
+    per lane) stores the same state bit for bit, through plain, graph and
+    checked steps."""
+    shape = (6, 24, 64)
+    kw = dict(tau=0.75, magic=0.2, delta_rho=2e-3, collision="trt", wall=wall,
+              spheres=inputs.random_spheres(shape, 4, (2.0, 4.0), seed=44), check_interval=20)
+    g0 = inputs.random_populations(shape, 1e-3, seed=45)
+    shapes = [(4, 1, False), (8, 2, False), (16, 8, False), (2, 2, False)]
+    if storage == "fp16":
+        shapes += [(2, 1, True), (8, 4, True)]
+    states = []
+    for waves, rows, pairs in shapes:
+        d = lbm.Domain(shape, storage=storage, **kw)
+        d.set_step_shape(waves, rows, pairs)
+        d.set_state(g0)
+        d.step(40)
+        d.run_to_residual(0.0, 40)
+        states.append(d.get_state())
+        d.close()
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
+
+
 def test_pair_shape_rejected_where_it_cannot_run():
     shape = (4, 6, 70)  # nx not a multiple of the 64-cell rows
     d = lbm.Domain(shape, tau=0.8, storage="fp16", mask=np.zeros(shape, np.uint8))
