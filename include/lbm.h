@@ -107,7 +107,9 @@ typedef struct {
 } lbm_sphere;
 
 typedef struct {
-  int32_t nx, ny, nz;     /* box edge in cells, each >= 1, nx*ny*nz < 2^31      */
+  int32_t nx, ny, nz;     /* box edge in cells, each >= 1, nx*ny*nz < 2^31,     */
+                          /* nx*ny < 2^32 / (19 * value bytes) (padded to whole */
+                          /* tiles; the kernels' in-plane offsets are 32-bit)   */
   double tau;             /* relaxation time 1/omega+, > 1/2; nu = (tau-1/2)/3  */
   double magic;           /* TRT Lambda in (0, 3/4] (Sec. 2.1); unused by SRT/MRT */
   double delta_rho;       /* density jump across the x-periodic plane           */
@@ -273,7 +275,9 @@ lbm_status lbm_drag(lbm_domain d, double F[3]);
  * every cell; lbm_run_to_residual tests each cell on the device every
  * check_interval steps and drops converged, unstable or finished cells from
  * later launches, so a run is a replayed graph of kernels with no host
- * decision inside.  lbm_init_equilibrium, lbm_set_state, lbm_get_state,
+ * decision inside; between replays the host reads the count of running
+ * cells and, once it falls to half or less, replays graphs that launch
+ * blocks only for the running ones (a device list).  lbm_init_equilibrium, lbm_set_state, lbm_get_state,
  * lbm_macroscopic and lbm_step act on the whole stack; lbm_mean_velocity,
  * lbm_permeability, lbm_drag and lbm_set_delta_rho are per-domain and
  * return LBM_ERR_STATE for a batch (use lbm_batch_results).  Storage must be

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lattice.hpp"
 
@@ -87,6 +88,11 @@ struct Tiling {
   }
 };
 
+// FP32 and FP64 states are cut into runs of 2^7 addresses for one domain and
+// of 2^6 for batches (every batch cell then starts on a run); every z plane
+// starts on a run (state_base).
+constexpr int kStepRunLog2 = 7, kBatchRunLog2 = 6;
+
 // Tiling::slot for a kernel's storage type, with the layout fixed at compile
 // time (16-bit values: direction planes, k * run_pitch + a; FP32 and FP64:
 // runs of 2^run_log2 addresses), so that the per-lane address is the cell
@@ -97,6 +103,40 @@ __device__ __forceinline__ long long state_slot(const Tiling& t, int k, long lon
     return k * t.run_pitch + a;
   else
     return ((((a >> t.run_log2) * kQ) + k) << t.run_log2) + (a & ((1LL << t.run_log2) - 1));
+}
+
+// Byte offset of direction k of the cell at address zstart + r, split into a
+// wavefront-uniform part (direction k and the z plane that starts at address
+// zstart, a whole number of runs) and a 32-bit part per lane (the in-plane
+// address r), so that a load is a scalar base plus a lane offset.  The host
+// keeps planes small enough for the lane part to fit in 32 bits.
+// The run length stays a run-time value here: the per-direction bases are
+// then computed on the scalar unit and every pull is a scalar base plus a
+// lane offset (512^3 sphere pack, FP32: 2.31 ms per step, against 2.37 ms
+// with the run length fixed at compile time, where the compiler folds the
+// direction offsets into 64-bit lane addresses, and 2.34-2.36 ms with 64-bit
+// lane addresses throughout).
+template <typename S>
+__device__ __forceinline__ long long state_base(const Tiling& t, int k, long long zstart) {
+  if constexpr (sizeof(S) == 2)
+    return 2LL * (k * t.run_pitch + zstart);
+  else  // zstart / run length runs of kQ directions before, then k directions
+    return (long long)sizeof(S) * (zstart * kQ + ((long long)k << t.run_log2));
+}
+template <typename S>
+__device__ __forceinline__ uint32_t state_lane(const Tiling& t, int r) {
+  if constexpr (sizeof(S) == 2) {
+    return 2u * (uint32_t)r;
+  } else {
+    const uint32_t run = (uint32_t)r >> t.run_log2, in = (uint32_t)r & ((1u << t.run_log2) - 1u);
+    return (uint32_t)sizeof(S) * (((run * (uint32_t)kQ) << t.run_log2) + in);
+  }
+}
+template <typename S, typename P>
+__device__ __forceinline__ P* state_at(P* base, const Tiling& t, int k, long long zstart, int r) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(base) + state_base<S>(t, k, zstart) +
+                              state_lane<S>(t, r));
 }
 
 // Element of direction k of the cell at address a: for direction planes the
@@ -124,6 +164,10 @@ struct StepParams {
   double s_e;         // MRT energy modes 1, 2
   double s_zeta;      // MRT remaining kinetic modes
   double sigma;       // 16-bit storage: stored h_k = sigma * g_k / w_k
+  float dec[3];       // ... h -> g factors w_k / sigma per weight class (rest, axis, diagonal)
+  float enc[3];       // ... g -> h factors sigma / w_k
+  // the rates and jumps above rounded to FP32 (the FP32 compute type)
+  float omega_pf, omega_mf, s_ef, s_zetaf, jump_axisf, jump_diagf;
   unsigned seed;      // stochastic rounding: per-step seed
   int wall;           // wall rule (lbm_wall) for the general wall template
   int solid_writes;   // batches: which solid cells store (solid_stores): 0, 1, 2
@@ -669,46 +713,67 @@ __device__ C general_wall_value(const S* __restrict__ src, const uint32_t* __res
 }
 
 
+// A parameter in the compute precision: FP64 kernels use the double, the
+// others the FP32 copy that the host rounded.
+template <typename C>
+__device__ __forceinline__ C prm(double d, float f) {
+  if constexpr (sizeof(C) == sizeof(float))
+    return f;
+  else
+    return d;
+}
+
+// Pressure jump of direction k in the units of the stored values (g units
+// for FP32 and FP64, g * sigma / w_k for the 16-bit formats).
+template <typename S>
+__device__ __forceinline__ typename ComputeOf<S>::type jump_stored(const StepParams& p, int k) {
+  using C = typename ComputeOf<S>::type;
+  const C j = wclass(k) == 1 ? prm<C>(p.jump_axis, p.jump_axisf) : prm<C>(p.jump_diag, p.jump_diagf);
+  if constexpr (Storage<S>::scaled)
+    return j * (C)p.enc[wclass(k)];
+  else
+    return j;
+}
+
 // The part of a node's time step after the pull: SBB / CLI wall links (the
-// general rules are applied by the caller), pressure jump, collision, and the
-// 19 values to store (out, in the storage format).  g holds the pulled raw
-// stored values (on a wall link: the stored coefficient a for CLI); own holds
-// the node's own stored values of directions 1..18 when it has wall links.
-// Returns the pre-collision moments (which the collision conserves) and
-// max_k |g*_k| / w_k of the stored result, for the optional reduction.
+// general rules are applied by the caller), pressure jump and collision.  g
+// holds the pulled raw stored values (on a wall link: the stored coefficient
+// a for CLI); own holds the node's own stored values of directions 1..18
+// when it has wall links.  edge_x must be true when a lane of the wavefront
+// lies on the box's x faces (x = 0 or nx - 1); it is wavefront-uniform, so
+// the wavefronts inside the box skip the jump's per-lane tests.  On return g
+// holds the new values in stored units, not yet rounded to the storage type;
+// mom the pre-collision moments (which the collision conserves) and
+// max_k |g*_k| / w_k of the result, for the optional reduction.
 template <typename S, int COLL, int WALL>
-__device__ __forceinline__ void finish_node(typename ComputeOf<S>::type (&g)[kQ],
-                                            const S (&own)[kQ], S (&out)[kQ],
-                                            const StepParams& p, int x, int c, uint32_t fl,
-                                            typename ComputeOf<S>::type (&mom)[5]) {
+__device__ __forceinline__ void finish_values(typename ComputeOf<S>::type (&g)[kQ],
+                                              const S (&own)[kQ], const StepParams& p, int x,
+                                              uint32_t fl, bool edge_x,
+                                              typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
   using St = Storage<S>;
+  static_assert(!(St::scaled && WALL == kGEN), "16-bit storage: SBB and CLI walls only");
   const int nx = p.nx;
-  // stored -> g factors per weight class (1 for unscaled storage)
-  C dec[3] = {(C)1, (C)1, (C)1};
-  if constexpr (St::scaled) {
-    const double is = 1.0 / p.sigma;
-    dec[0] = (C)(kLat.w[0] * is);
-    dec[1] = (C)(kLat.w[1] * is);
-    dec[2] = (C)(kLat.w[7] * is);
-  }
   if constexpr (WALL != kGEN) {
     if (fl & kLinkMask) {
+      // in stored units: every term of a link's value is a value of
+      // direction k or of its opposite j, which share a weight and so a
+      // storage scale
 #pragma unroll
       for (int k = 1; k < kQ; ++k) {
         if (fl & (1u << k)) {
           const int j = kLat.opp[k];
-          const C own_j = (C)St::to_float(own[j]) * dec[wclass(j)];
+          const C own_j = (C)St::to_float(own[j]);
           if constexpr (WALL == kCLI) {
             const C a = g[k];
-            const C own_k = (C)St::to_float(own[k]) * dec[wclass(k)];
+            const C own_k = (C)St::to_float(own[k]);
             // g_j at the second node x_f2 = x + e_k (away from the wall) is
             // what this node pulls in direction j, so g[j] already holds it
             // (raw); it is read across the x-periodic plane with the pressure
             // jump.  If x_f2 is solid, g[j] is a coefficient and a = 0.
-            C far_j = g[j] * dec[wclass(j)];
-            if (kLat.ex[k] == 1 && x == nx - 1) far_j -= (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
-            if (kLat.ex[k] == -1 && x == 0) far_j += (C)(kLat.w[k] == 1.0 / 18.0 ? p.jump_axis : p.jump_diag);
+            C far_j = g[j];
+            if (kLat.ex[k] == 1 && x == nx - 1) far_j -= jump_stored<S>(p, k);
+            if (kLat.ex[k] == -1 && x == 0) far_j += jump_stored<S>(p, k);
             g[k] = a * far_j - a * own_k + own_j;
           } else {
             g[k] = own_j;
@@ -718,70 +783,98 @@ __device__ __forceinline__ void finish_node(typename ComputeOf<S>::type (&g)[kQ]
     }
   }
   if constexpr (St::scaled) {
-    g[0] *= dec[0];
 #pragma unroll
-    for (int k = 1; k < kQ; ++k)
-      if (!(fl & (1u << k))) g[k] *= dec[wclass(k)];
+    for (int k = 0; k < kQ; ++k) g[k] *= (C)p.dec[wclass(k)];
   }
 
   // periodic pressure drop on pulls across the x-plane (not on wall links)
-  if (x == 0) {
-    const C ja = (C)p.jump_axis, jd = (C)p.jump_diag;
-    if (!(fl & (1u << 1))) g[1] += ja;
-    if (!(fl & (1u << 7))) g[7] += jd;
-    if (!(fl & (1u << 9))) g[9] += jd;
-    if (!(fl & (1u << 11))) g[11] += jd;
-    if (!(fl & (1u << 13))) g[13] += jd;
-  }
-  if (x == nx - 1) {
-    const C ja = (C)p.jump_axis, jd = (C)p.jump_diag;
-    if (!(fl & (1u << 2))) g[2] -= ja;
-    if (!(fl & (1u << 8))) g[8] -= jd;
-    if (!(fl & (1u << 10))) g[10] -= jd;
-    if (!(fl & (1u << 12))) g[12] -= jd;
-    if (!(fl & (1u << 14))) g[14] -= jd;
+  if (edge_x) {
+    if (x == 0) {
+      const C ja = prm<C>(p.jump_axis, p.jump_axisf), jd = prm<C>(p.jump_diag, p.jump_diagf);
+      if (!(fl & (1u << 1))) g[1] += ja;
+      if (!(fl & (1u << 7))) g[7] += jd;
+      if (!(fl & (1u << 9))) g[9] += jd;
+      if (!(fl & (1u << 11))) g[11] += jd;
+      if (!(fl & (1u << 13))) g[13] += jd;
+    }
+    if (x == nx - 1) {
+      const C ja = prm<C>(p.jump_axis, p.jump_axisf), jd = prm<C>(p.jump_diag, p.jump_diagf);
+      if (!(fl & (1u << 2))) g[2] -= ja;
+      if (!(fl & (1u << 8))) g[8] -= jd;
+      if (!(fl & (1u << 10))) g[10] -= jd;
+      if (!(fl & (1u << 12))) g[12] -= jd;
+      if (!(fl & (1u << 14))) g[14] -= jd;
+    }
   }
 
   moments(g, mom[0], mom[1], mom[2], mom[3]);
   if constexpr (COLL == kSRT) {
-    collide_srt<C>(g, (C)p.omega_p);
+    collide_srt<C>(g, prm<C>(p.omega_p, p.omega_pf));
   } else if constexpr (COLL == kTRT) {
-    collide_trt<C>(g, (C)p.omega_p, (C)p.omega_m);
+    collide_trt<C>(g, prm<C>(p.omega_p, p.omega_pf), prm<C>(p.omega_m, p.omega_mf));
   } else {
-    collide_mrt<C>(g, (C)p.omega_p, (C)p.s_e, (C)p.s_zeta);
-  }
-
-  C enc[3] = {(C)1, (C)1, (C)1};
-  if constexpr (St::scaled) {
-    enc[0] = (C)(p.sigma / kLat.w[0]);
-    enc[1] = (C)(p.sigma / kLat.w[1]);
-    enc[2] = (C)(p.sigma / kLat.w[7]);
-  }
-  if constexpr (IsStochastic<S>::value) {
-    // one finalised hash per cell and step; direction k takes the high bits
-    // of (base + k * golden) * odd constant (multiplicative hashing)
-    const uint32_t base = hash32((uint32_t)c * 19u + p.seed);
-#pragma unroll
-    for (int k = 0; k < kQ; ++k)
-      out[k] = St::from_float_sr(g[k] * enc[wclass(k)],
-                                 (base + (uint32_t)k * 0x9e3779b9u) * 0x85ebca6bu);
-  } else {
-#pragma unroll
-    for (int k = 0; k < kQ; ++k) out[k] = St::from_float(g[k] * enc[wclass(k)]);
+    collide_mrt<C>(g, prm<C>(p.omega_p, p.omega_pf), prm<C>(p.s_e, p.s_ef),
+                   prm<C>(p.s_zeta, p.s_zetaf));
   }
   C m = (C)0;
 #pragma unroll
   for (int k = 0; k < kQ; ++k) m = fmax(m, fabs(g[k]) * (C)(1.0 / kLat.w[k]));
   mom[4] = m;
+  if constexpr (St::scaled) {
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) g[k] *= (C)p.enc[wclass(k)];
+  }
+}
+
+// Stochastic rounding's random words: one finalised hash per cell and step,
+// then direction k takes the high bits of (base + k * golden) * odd constant
+// (multiplicative hashing).
+__device__ __forceinline__ uint32_t sr_base(int c, unsigned seed) {
+  return hash32((uint32_t)c * 19u + seed);
+}
+__device__ __forceinline__ uint32_t sr_word(uint32_t base, int k) {
+  return (base + (uint32_t)k * 0x9e3779b9u) * 0x85ebca6bu;
+}
+
+// Round a node's new values (stored units) to the storage type.
+template <typename S>
+__device__ __forceinline__ void round_node(const typename ComputeOf<S>::type (&v)[kQ],
+                                           const StepParams& p, int c, S (&out)[kQ]) {
+  using St = Storage<S>;
+  if constexpr (IsStochastic<S>::value) {
+    const uint32_t base = sr_base(c, p.seed);
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) out[k] = St::from_float_sr(v[k], sr_word(base, k));
+  } else {
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) out[k] = St::from_float(v[k]);
+  }
+}
+
+template <typename S, int COLL, int WALL>
+__device__ __forceinline__ void finish_node(typename ComputeOf<S>::type (&g)[kQ],
+                                            const S (&own)[kQ], S (&out)[kQ],
+                                            const StepParams& p, int x, int c, uint32_t fl,
+                                            bool edge_x,
+                                            typename ComputeOf<S>::type (&mom)[5]) {
+  finish_values<S, COLL, WALL>(g, own, p, x, fl, edge_x, mom);
+  round_node<S>(g, p, c, out);
 }
 
 // One time step for the node (x, y, z), fluid, with flag word fl: pull (one
-// lane, one node), the general wall rules, then finish_node.
-template <typename S, int COLL, int WALL>
+// lane, one node), the general wall rules, then finish_node (edge_x as
+// there).  SPLIT selects pulls from scalar per-direction bases plus 32-bit
+// lane offsets (state_at); without it every lane forms 64-bit addresses.
+// The split form needs about 40 more scalar registers; in the kernels with
+// the general wall rules and in the batch kernel it made the compiler spill
+// scalar registers (general rules 5-11% slower at 512^3, batches 6%), so only
+// the single-domain SBB / CLI kernels use it.
+template <typename S, int COLL, int WALL, bool SPLIT>
 __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[kQ],
                                             const uint32_t* __restrict__ flags,
                                             const StepParams& p, int x, int y, int z, int c,
-                                            uint32_t fl, typename ComputeOf<S>::type (&mom)[5]) {
+                                            uint32_t fl, bool edge_x,
+                                            typename ComputeOf<S>::type (&mom)[5]) {
   using C = typename ComputeOf<S>::type;
   using St = Storage<S>;
   const int nx = p.nx, plane = p.t.plane;
@@ -799,8 +892,14 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
   C g[kQ];
   // pull: direction k arrives from x - e_k (raw stored values)
 #pragma unroll
-  for (int k = 0; k < kQ; ++k)
-    g[k] = (C)St::to_float(*state_ptr<S>(src, p.t, k, n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])));
+  for (int k = 0; k < kQ; ++k) {
+    if constexpr (SPLIT)
+      g[k] = (C)St::to_float(*state_at<S>(src, p.t, k, n.zs[1 - kLat.ez[k]],
+                                          n.xs[1 - kLat.ex[k]] + n.ys[1 - kLat.ey[k]]));
+    else
+      g[k] = (C)St::to_float(
+          *state_ptr<S>(src, p.t, k, n.at(-kLat.ex[k], -kLat.ey[k], -kLat.ez[k])));
+  }
 
   // wall links: the pulled raw value is the stored coefficient a (CLI) or
   // the wall distance q (general rules)
@@ -810,7 +909,9 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
     // need g_j and g_k at x), all requested before the first use: one memory
     // round trip per boundary node instead of one per link direction (512^3
     // sphere pack, FP32 CLI: 2.84 -> 2.56 ms per step).  IEBB's moments at x
-    // come from the same values.
+    // come from the same values.  (64-bit lane addresses: with scalar bases
+    // per direction as for the pulls, the boundary wavefronts' extra scalar
+    // work made the 512^3 sphere-pack step 3% slower.)
 #pragma unroll
     for (int k = 1; k < kQ; ++k) own[k] = *state_ptr<S>(src, p.t, k, c);
     if constexpr (WALL == kGEN) {
@@ -839,7 +940,7 @@ __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[
       }
     }
   }
-  finish_node<S, COLL, WALL>(g, own, out, p, x, c, fl, mom);
+  finish_node<S, COLL, WALL>(g, own, out, p, x, c, fl, edge_x, mom);
 }
 
 // The 19 values a solid cell writes: its wall-link slots (flag bit k: the
@@ -888,15 +989,16 @@ __device__ __forceinline__ void nontemporal_store(S v, S* p) {
     __builtin_nontemporal_store(v, p);
 }
 
-template <typename S, bool NT>
+template <typename S, bool NT, bool SPLIT>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const S (&out)[kQ],
-                                           const Tiling& t, int c) {
+                                           const Tiling& t, long long zstart, int r) {
 #pragma unroll
   for (int k = 0; k < kQ; ++k) {
+    S* q = SPLIT ? state_at<S>(dst, t, k, zstart, r) : state_ptr<S>(dst, t, k, (int)zstart + r);
     if constexpr (NT)
-      nontemporal_store(out[k], state_ptr<S>(dst, t, k, c));
+      nontemporal_store(out[k], q);
     else
-      *state_ptr<S>(dst, t, k, c) = out[k];
+      *q = out[k];
   }
 }
 
@@ -919,7 +1021,8 @@ __device__ __forceinline__ void store_side(const StepParams& p, uint8_t cls, int
 // hold 64 consecutive addresses.  inside is false for padding cells and for
 // tiles past the end of the plane (c must not be used then).
 struct TileCell {
-  int x, y, c;
+  int x, y, c;  // coordinates and address
+  int r;        // address within the z plane
   bool inside;
 };
 __device__ __forceinline__ TileCell tile_cell(const Tiling& t, int z) {
@@ -930,18 +1033,24 @@ __device__ __forceinline__ TileCell tile_cell(const Tiling& t, int z) {
   r.x = (tx << t.tw_log2) + (l & ((1 << t.tw_log2) - 1));
   r.y = (ty << t.th_log2) + (l >> t.tw_log2);
   r.inside = ty < t.nty && r.x < t.nx && r.y < t.ny;
-  r.c = (tile << 6) + l + z * t.plane;
+  r.r = (tile << 6) + l;
+  r.c = r.r + z * t.plane;
   return r;
 }
 
 // Unit column and tile row of this wavefront in a step workgroup (the bw x
-// bh arrangement of StepParams; workgroups run along a band of tile rows,
-// then the next band).  Units past the row end give u >= units per row.
+// bh arrangement of StepParams; the grid is nbx workgroups along a band of
+// bh tile rows times the bands times the z planes).  Units past the row end
+// give u >= units per row.
 __device__ __forceinline__ void step_unit(const StepParams& p, int& u, int& ty) {
   const int j = threadIdx.y;
-  const int bx = blockIdx.x % p.nbx, by = blockIdx.x / p.nbx;
-  u = bx * p.bw + j % p.bw;
-  ty = by * p.bh + j / p.bw;
+  u = blockIdx.x * p.bw + j % p.bw;
+  ty = blockIdx.y * p.bh + j / p.bw;
+}
+
+// Partial-sum slot of a step workgroup.
+__device__ __forceinline__ long long step_block_id() {
+  return blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
 }
 
 // tile_cell for the single-domain step: the tile is the wavefront's unit.
@@ -954,7 +1063,8 @@ __device__ __forceinline__ TileCell step_tile_cell(const StepParams& p, int z) {
   r.x = (tx << t.tw_log2) + (l & ((1 << t.tw_log2) - 1));
   r.y = (ty << t.th_log2) + (l >> t.tw_log2);
   r.inside = tx < t.ntx && ty < t.nty && r.x < t.nx && r.y < t.ny;
-  r.c = ((ty * t.ntx + tx) << 6) + l + z * t.plane;
+  r.r = ((ty * t.ntx + tx) << 6) + l;
+  r.c = r.r + z * t.plane;
   return r;
 }
 
@@ -980,16 +1090,18 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
                                                             const StepParams p,
                                                             double* __restrict__ partials) {
   using C = typename ComputeOf<S>::type;
+  constexpr bool kSplit = WALL != kGEN;  // (update_node)
   const int z = blockIdx.z;
   const TileCell tc = step_tile_cell(p, z);
   const uint8_t k = tc.inside ? cls[tc.c] : kClsSolid;
+  const bool edge_x = __ballot(tc.x == 0 || tc.x == p.nx - 1) != 0;
   if constexpr (!RED) {
     if (k & kClsSolid) return;
     const uint32_t fl = flag_word(k, flags, tc.c);
     S out[kQ];
     C mom[5];
-    update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
-    store_node<S, NT>(dst, out, p.t, tc.c);
+    update_node<S, COLL, WALL, kSplit>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, edge_x, mom);
+    store_node<S, NT, kSplit>(dst, out, p.t, (long long)z * p.t.plane, tc.r);
     if constexpr (WALL == kGEN) store_side<C>(p, k, tc.c, mom);
   } else {
     double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -997,8 +1109,9 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
       const uint32_t fl = flag_word(k, flags, tc.c);
       S out[kQ];
       C mom[5];
-      update_node<S, COLL, WALL>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, mom);
-      store_node<S, NT>(dst, out, p.t, tc.c);
+      update_node<S, COLL, WALL, kSplit>(src, out, flags, p, tc.x, tc.y, z, tc.c, fl, edge_x,
+                                         mom);
+      store_node<S, NT, kSplit>(dst, out, p.t, (long long)z * p.t.plane, tc.r);
       if constexpr (WALL == kGEN) store_side<C>(p, k, tc.c, mom);
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
       const double u2 = ux * ux + uy * uy + uz * uz;
@@ -1013,8 +1126,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
       v[6] = isfinite((double)mom[4]) ? (double)mom[4] : 0.0;
     }
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
-    const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.z;
-    block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
+    block_reduce<kRedVals>(v, kind, partials + step_block_id() * kRedVals);
   }
 }
 
@@ -1072,6 +1184,26 @@ __device__ __forceinline__ uint32_t bits_of(S v) {
   return (uint32_t)__builtin_bit_cast(uint16_t, v);
 }
 
+// Half h of a pair word set to v rounded to the 16-bit type S, the other
+// half kept from w.  The stochastic formats round with the conversion
+// instruction itself (its high-half form keeps the low half) and the cell's
+// own random word r, so each half equals round_node's result for its cell.
+template <typename S, int H>
+__device__ __forceinline__ uint32_t put_half(uint32_t w, float v, uint32_t r) {
+  if constexpr (std::is_same<S, fp16s_t>::value) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(
+        uint32_t, __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h2, w), v, r, H != 0));
+  } else if constexpr (std::is_same<S, bf16s_t>::value) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(
+        uint32_t, __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(b2, w), v, r, H != 0));
+  } else {
+    const uint32_t b = bits_of<S>(Storage<S>::from_float(v));
+    return H ? (w & 0xffffu) | (b << 16) : (w & 0xffff0000u) | b;
+  }
+}
+
 template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __restrict__ src,
                                                                  S* __restrict__ dst,
@@ -1085,9 +1217,11 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
   const Tiling& t = p.t;
   const int z = blockIdx.z;
   const PairCell pc = pair_cell(p);
-  const int c = pc.a + z * t.plane;  // cell A
-  const uint32_t cl2 = pc.inside ? (uint32_t)(*reinterpret_cast<const uint16_t*>(cls + c))
-                                 : (uint32_t)(kClsSolid | (kClsSolid << 8));
+  const long long zplane = (long long)z * t.plane;  // address of plane z's first cell
+  const int c = pc.a + (int)zplane;                 // cell A
+  const uint32_t cl2 =
+      pc.inside ? (uint32_t)(*reinterpret_cast<const uint16_t*>(cls + zplane + (uint32_t)pc.a))
+                : (uint32_t)(kClsSolid | (kClsSolid << 8));
   const bool solid_a = cl2 & kClsSolid, solid_b = (cl2 >> 8) & kClsSolid;
   const bool live = !(solid_a && solid_b);
   const unsigned long long ball = __ballot(live);
@@ -1096,49 +1230,56 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
     // the lanes of a DPP row with a fluid cell read their words (neighbours
     // within the row need them, solid or not)
     const bool row_reads = pc.inside && ((ball >> (threadIdx.x & 48)) & 0xffffull) != 0;
-    const int nx = p.nx, plane = t.plane;
-    const int xs_lo = t.xpart(pc.x == 0 ? nx - 2 : pc.x - 2);
-    const int xs_0 = t.xpart(pc.x);
-    const int xs_hi = t.xpart(pc.x + 2 == nx ? 0 : pc.x + 2);
-    int ys[3], zs[3];
-    ys[0] = t.ypart(pc.y == 0 ? p.ny - 1 : pc.y - 1);
-    ys[1] = t.ypart(pc.y);
-    ys[2] = t.ypart(pc.y == p.ny - 1 ? 0 : pc.y + 1);
-    zs[0] = (z == 0 ? p.nz - 1 : z - 1) * plane;
-    zs[1] = z * plane;
-    zs[2] = (z == p.nz - 1 ? 0 : z + 1) * plane;
-    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+    const int nx = p.nx;
+    // Word addresses as a wavefront-uniform base (direction plane k, source
+    // z plane) plus a 32-bit byte offset per lane, twice the in-plane cell
+    // address of the pair's even cell: the x parts of x - 2, x, x + 2 and
+    // the y parts of y - 1, y, y + 1 (wrapped) are added once per (x, y)
+    // combination.  Lanes that need no word read the plane's first word;
+    // lanes at no tile or DPP-row edge read their own word for the edge load.
+    const uint32_t xo = row_reads ? 2u * (uint32_t)t.xpart(pc.x) : 0u;
+    const uint32_t xlo =
+        row_reads && pc.edge_lo ? 2u * (uint32_t)t.xpart(pc.x == 0 ? nx - 2 : pc.x - 2) : xo;
+    const uint32_t xhi =
+        row_reads && pc.edge_hi ? 2u * (uint32_t)t.xpart(pc.x + 2 == nx ? 0 : pc.x + 2) : xo;
+    uint32_t yo[3];
+    yo[0] = row_reads ? 2u * (uint32_t)t.ypart(pc.y == 0 ? p.ny - 1 : pc.y - 1) : 0u;
+    yo[1] = row_reads ? 2u * (uint32_t)t.ypart(pc.y) : 0u;
+    yo[2] = row_reads ? 2u * (uint32_t)t.ypart(pc.y == p.ny - 1 ? 0 : pc.y + 1) : 0u;
+    const long long zb[3] = {2LL * (z == 0 ? p.nz - 1 : z - 1) * t.plane, 2LL * zplane,
+                             2LL * (z == p.nz - 1 ? 0 : z + 1) * t.plane};
+    const char* sb = reinterpret_cast<const char*>(src);
 
     // pull: one word per direction with cell A's pulled value in the low
     // half and cell B's in the high half (direction k from x - e_k)
     // Every lane issues every load (no branches, so that all of them are in
-    // flight together): lanes that need no word read address 0 of the plane,
-    // and the lanes that need no edge word read their own word again.  All
-    // loads come before the first DPP shift, which waits for its word.
+    // flight together).  All loads come before the first DPP shift, which
+    // waits for its word.
     uint32_t raw[kQ], edge[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
       const int ex = kLat.ex[k];
-      const int row = ys[1 - kLat.ey[k]] + zs[1 - kLat.ez[k]];
-      // 16-bit states are direction planes: plane k's words, indexed by half
-      // the (even) cell address
-      const uint32_t* sk = s32 + (state_slot<S>(t, k, 0) >> 1);
-      const int a0 = row_reads ? xs_0 + row : 0;
-      raw[k] = sk[a0 >> 1];
-      if (ex == 1) edge[k] = sk[(row_reads && pc.edge_lo ? xs_lo + row : a0) >> 1];
-      if (ex == -1) edge[k] = sk[(row_reads && pc.edge_hi ? xs_hi + row : a0) >> 1];
+      // 16-bit states are direction planes: plane k, source z plane
+      const char* bk = sb + 2LL * state_slot<S>(t, k, 0) + zb[1 - kLat.ez[k]];
+      const uint32_t yk = yo[1 - kLat.ey[k]];
+      raw[k] = *reinterpret_cast<const uint32_t*>(bk + (xo + yk));
+      if (ex == 1) edge[k] = *reinterpret_cast<const uint32_t*>(bk + (xlo + yk));
+      if (ex == -1) edge[k] = *reinterpret_cast<const uint32_t*>(bk + (xhi + yk));
     }
     // Boundary pairs: both flag words and the pair's own words, requested
     // with the pulls (one memory round trip): wall rules of link cells, and
     // the unchanged half of a pair with one solid cell (whose fluid partner
     // then has an x link).
+    const uint32_t ab = 2u * (uint32_t)pc.a;
     const bool links = live && (cl2 & (kClsLinks | (kClsLinks << 8))) != 0;
     uint2 flw = make_uint2(0u, 0u);
     uint32_t own_w[kQ];
     if (links) {
       flw = *reinterpret_cast<const uint2*>(flags + c);
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) own_w[k] = s32[(state_slot<S>(t, k, 0) >> 1) + (c >> 1)];
+      for (int k = 0; k < kQ; ++k)
+        own_w[k] = *reinterpret_cast<const uint32_t*>(sb + 2LL * state_slot<S>(t, k, 0) +
+                                                      zb[1] + ab);
     }
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
@@ -1157,36 +1298,27 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
       }
     }
 
-    {
-      uint32_t outw[kQ];
+    // a lane of the wavefront on the box's x faces (cell A at x = 0, cell B
+    // at x = nx - 1): wavefront-uniform
+    const bool edge_x = __ballot(pc.x == 0 || pc.x + 2 == nx) != 0;
+    C ga[kQ], gb[kQ];  // cell A (h = 0), cell B (h = 1)
 #pragma unroll
-      for (int k = 0; k < kQ; ++k) outw[k] = 0;
-      // cell A (h = 0) and cell B (h = 1)
+    for (int k = 0; k < kQ; ++k) {
+      ga[k] = (C)Storage<S>::to_float(half_of<S>(raw[k], 0));
+      gb[k] = (C)Storage<S>::to_float(half_of<S>(raw[k], 1));
+    }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int sh = 16 * h;
-        const bool solid = h ? solid_b : solid_a;
+    for (int h = 0; h < 2; ++h) {
+      const bool solid = h ? solid_b : solid_a;
+      C(&g)[kQ] = h ? gb : ga;
+      if (!solid) {
         const uint32_t clh = (cl2 >> (8 * h)) & 0xffu;  // class bytes: A low, B high
-        if (solid) {
-          // a solid cell beside a fluid one keeps its (constant) values
-          if (!(h ? solid_a : solid_b)) {
-#pragma unroll
-            for (int k = 0; k < kQ; ++k) outw[k] |= (own_w[k] >> sh & 0xffffu) << sh;
-          }
-          continue;
-        }
         const uint32_t fl = (clh & kClsLinks) ? (h ? flw.y : flw.x) : 0u;
         S own[kQ];
 #pragma unroll
         for (int k = 1; k < kQ; ++k) own[k] = half_of<S>(own_w[k], h);
-        C g[kQ];
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) g[k] = (C)Storage<S>::to_float(half_of<S>(raw[k], h));
-        S out[kQ];
         C mom[5];
-        finish_node<S, COLL, WALL>(g, own, out, p, pc.x + h, c + h, fl, mom);
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) outw[k] |= bits_of<S>(out[k]) << sh;
+        finish_values<S, COLL, WALL>(g, own, p, pc.x + h, fl, edge_x, mom);
         if constexpr (RED) {
           const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
           const double u2 = ux * ux + uy * uy + uz * uz;
@@ -1201,23 +1333,40 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
           v[6] = fmax(v[6], isfinite((double)mom[4]) ? (double)mom[4] : 0.0);
         }
       }
-      if (live) {
-        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+    }
+    // round into the pair words, cell A's half first (into the register of
+    // A's value: the word's other initial bits are never used); every lane
+    // rounds both halves, and a solid cell beside a fluid one then gets its
+    // (constant) stored values back
+    const uint32_t base_a = IsStochastic<S>::value ? sr_base(c, p.seed) : 0u;
+    const uint32_t base_b = IsStochastic<S>::value ? sr_base(c + 1, p.seed) : 0u;
+    uint32_t outw[kQ];
 #pragma unroll
-        for (int k = 0; k < kQ; ++k) {
-          uint32_t* q = d32 + (state_slot<S>(t, k, 0) >> 1) + (c >> 1);
-          if constexpr (NT)
-            __builtin_nontemporal_store(outw[k], q);
-          else
-            *q = outw[k];
-        }
+    for (int k = 0; k < kQ; ++k)
+      outw[k] = put_half<S, 1>(
+          put_half<S, 0>(__builtin_bit_cast(uint32_t, ga[k]), ga[k], sr_word(base_a, k)),
+          gb[k], sr_word(base_b, k));
+    const bool mixed = links && solid_a != solid_b;
+    if (__ballot(mixed) != 0 && mixed) {
+      const uint32_t keep = solid_a ? 0x0000ffffu : 0xffff0000u;
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) outw[k] = (own_w[k] & keep) | (outw[k] & ~keep);
+    }
+    if (live) {
+      char* db = reinterpret_cast<char*>(dst);
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        uint32_t* q = reinterpret_cast<uint32_t*>(db + 2LL * state_slot<S>(t, k, 0) + zb[1] + ab);
+        if constexpr (NT)
+          __builtin_nontemporal_store(outw[k], q);
+        else
+          *q = outw[k];
       }
     }
   }
   if constexpr (RED) {
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 1, 0};
-    const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.z;
-    block_reduce<kRedVals>(v, kind, partials + b * kRedVals);
+    block_reduce<kRedVals>(v, kind, partials + step_block_id() * kRedVals);
   }
 }
 
@@ -1227,19 +1376,28 @@ __global__ __launch_bounds__(kStepThreads) void step_pair_kernel(const S* __rest
 // cell_size = nz planes of the cell's tiling).  Each block covers blockDim.y
 // consecutive tiles of zper consecutive z planes of one cell (zper divides
 // nz), reads that cell's parameters from a device table and skips inactive
-// (converged or stopped) cells.  Block ids of cell b are contiguous, so the
-// partial sums of a cell form one segment.  p.solid_writes selects which
-// solid cells also store (solid_stores, solid_node).
+// (converged or stopped) cells.  The grid's z runs over cell slots times the
+// cell's z blocks: slot j is cell j, or with a list (the running cells in
+// order, *n_list of them, rewritten by every convergence check) cell
+// list[j], so that a run whose cells have mostly stopped launches blocks for
+// the running ones only; slots from *n_list on return at once.  The partial
+// sums of cell b form one segment of blocks_per_cell entries wherever its
+// blocks ran.  p.solid_writes selects which solid cells also store
+// (solid_stores, solid_node).
 
 template <typename S, int COLL, int WALL, bool RED, bool NT>
 __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ cls,
     const uint32_t* __restrict__ flags, const StepParams* __restrict__ cells,
-    const int* __restrict__ active, int nz_cell, long long cell_size, int zper,
+    const int* __restrict__ active, const int* __restrict__ list,
+    const int* __restrict__ n_list, int nz_cell, long long cell_size, int zper,
     double* __restrict__ partials) {
   using C = typename ComputeOf<S>::type;
-  const int zz0 = blockIdx.z * zper;
-  const int b = zz0 / nz_cell;
+  const int zblocks = nz_cell / zper;
+  const int slot = blockIdx.z / zblocks;
+  const int zb = blockIdx.z - slot * zblocks;  // z block within the cell
+  if (list && slot >= *n_list) return;
+  const int b = list ? list[slot] : slot;
   if (!active[b]) return;
   const StepParams p = cells[b];
   const long long off = (long long)b * cell_size;
@@ -1251,21 +1409,22 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
   const uint32_t* f = flags + off;
   double v[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = 0; i < zper; ++i) {
-    const int z = zz0 + i - b * nz_cell;
+    const int z = zb * zper + i;
     const TileCell tc = tile_cell(p.t, z);
     const int c = tc.c;
     const uint8_t k = tc.inside ? cl[c] : kClsSolid;
     const bool solid = k & kClsSolid;
     const uint32_t fl = tc.inside ? flag_word(k, f, c) : kSolid;
     const unsigned long long fluid = __ballot(!solid);
+    const bool edge_x = __ballot(tc.x == 0 || tc.x == p.nx - 1) != 0;
     if (!solid_stores<S>(p.solid_writes, solid, fluid)) continue;
     S out[kQ];
     C mom[5];
     if (solid)
       solid_node<S>(s, out, p.t, c, fl);
     else
-      update_node<S, COLL, WALL>(s, out, f, p, tc.x, tc.y, z, c, fl, mom);
-    if (tc.inside) store_node<S, NT>(d, out, p.t, c);
+      update_node<S, COLL, WALL, false>(s, out, f, p, tc.x, tc.y, z, c, fl, edge_x, mom);
+    if (tc.inside) store_node<S, NT, false>(d, out, p.t, (long long)z * p.t.plane, tc.r);
     if (solid) continue;
     if constexpr (RED) {
       const double rho = mom[0], ux = mom[1], uy = mom[2], uz = mom[3];
@@ -1282,7 +1441,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_step_kernel(
   }
   if constexpr (RED) {
     const int kind[kRedVals] = {0, 0, 0, 0, 1, 0, 0, 0};
-    const long long blk = blockIdx.x + (long long)gridDim.x * blockIdx.z;
+    const long long blk = blockIdx.x + (long long)gridDim.x * ((long long)b * zblocks + zb);
     block_reduce<kRedVals>(v, kind, partials + blk * kRedVals);
   }
 }
@@ -1326,62 +1485,87 @@ __global__ __launch_bounds__(kRedThreads) void cell_reduce_kernel(const double* 
 // Convergence test of every running cell after a check step (one block):
 // residual |U - U_prev| / |U| below tol three times in a row -> converged;
 // non-finite or |u| above the sound speed -> unstable; step limit -> stop.
-// active[b] and the count of running cells are rewritten.
+// active[b], the running cells in order (list) and their count are
+// rewritten.
 __global__ __launch_bounds__(1024) void batch_check_kernel(const double* __restrict__ results,
                                                            CellStatus* __restrict__ st,
                                                            int* __restrict__ active,
+                                                           int* __restrict__ list,
                                                            int* __restrict__ n_active, int n_cells,
                                                            double inv_cell_size, double tol,
                                                            long long max_steps, int interval,
                                                            int parity_now) {
   __shared__ int count[32];
-  int mine = 0;
-  for (int b = threadIdx.x; b < n_cells; b += blockDim.x) {
-    CellStatus c = st[b];
-    if (c.status == 0) {
-      c.steps += interval;
-      const double* r = results + (long long)b * kRedVals;
-      const double U = r[0] * inv_cell_size;
-      c.u[0] = U;
-      c.u[1] = r[1] * inv_cell_size;
-      c.u[2] = r[2] * inv_cell_size;
-      c.max_u2 = r[4];
-      if (r[5] > 0 || !isfinite(U) || r[4] > 1.0 / 3.0) {
-        c.status = 2;
-      } else {
-        c.res = U != 0.0 ? fabs(U - c.prev_u) / fabs(U) : (U == c.prev_u ? 0.0 : INFINITY);
-        c.prev_u = U;
-        c.below = c.res < tol ? c.below + 1 : 0;
-        if (c.below >= 3) c.status = 1;
-        else if (c.steps >= max_steps) c.status = 3;
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  // chunks of blockDim.x cells (every thread runs every chunk, so that the
+  // block-wide scans below see all of them)
+  for (int b0 = 0; b0 < n_cells; b0 += blockDim.x) {
+    const int b = b0 + threadIdx.x;
+    int running = 0;
+    if (b < n_cells) {
+      CellStatus c = st[b];
+      if (c.status == 0) {
+        c.steps += interval;
+        const double* r = results + (long long)b * kRedVals;
+        const double U = r[0] * inv_cell_size;
+        c.u[0] = U;
+        c.u[1] = r[1] * inv_cell_size;
+        c.u[2] = r[2] * inv_cell_size;
+        c.max_u2 = r[4];
+        if (r[5] > 0 || !isfinite(U) || r[4] > 1.0 / 3.0) {
+          c.status = 2;
+        } else {
+          c.res = U != 0.0 ? fabs(U - c.prev_u) / fabs(U) : (U == c.prev_u ? 0.0 : INFINITY);
+          c.prev_u = U;
+          c.below = c.res < tol ? c.below + 1 : 0;
+          if (c.below >= 3) c.status = 1;
+          else if (c.steps >= max_steps) c.status = 3;
+        }
+        if (c.status != 0) c.parity = parity_now;
+        st[b] = c;
       }
-      if (c.status != 0) c.parity = parity_now;
-      st[b] = c;
+      active[b] = c.status == 0;
+      running = c.status == 0;
     }
-    active[b] = c.status == 0;
-    mine += c.status == 0;
+    // position of this cell among the chunk's running cells: inclusive scan
+    // within the wavefront, then the wavefront totals in order
+    int pre = running;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(pre, off, 64);
+      if (lane >= off) pre += o;
+    }
+    if (lane == 63) count[wv] = pre;
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wv; ++w) before += count[w];
+    if (running) list[before + pre - 1] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = base;
+      for (int w = 0; w < nw; ++w) t += count[w];
+      base = t;
+    }
+    __syncthreads();
   }
-  // block sum of running cells (wavefront shuffles, then LDS)
-  for (int off = 32; off > 0; off >>= 1) mine += __shfl_down(mine, off, 64);
-  if ((threadIdx.x & 63) == 0) count[threadIdx.x >> 6] = mine;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += count[w];
-    *n_active = t;
-  }
+  if (threadIdx.x == 0) *n_active = base;
 }
 
-// Start of a batch run: every cell running, counters cleared.
+// Start of a batch run: every cell running (and listed), counters cleared.
 __global__ void batch_reset_kernel(CellStatus* __restrict__ st, int* __restrict__ active,
+                                   int* __restrict__ list, int* __restrict__ n_active,
                                    int n_cells, int parity) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) *n_active = n_cells;
   if (b >= n_cells) return;
   CellStatus c{};
   c.res = INFINITY;
   c.parity = parity;
   st[b] = c;
   active[b] = 1;
+  list[b] = b;
 }
 
 __global__ void fill_int_kernel(int* __restrict__ a, int n, int v) {

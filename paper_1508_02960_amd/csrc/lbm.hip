@@ -74,12 +74,14 @@ struct lbm_domain_s {
   int* d_active_all = nullptr;  // all ones, for lbm_step
   CellStatus* d_status = nullptr;
   double* d_results = nullptr;
-  int* d_nactive = nullptr;
+  int* d_nactive = nullptr;     // running cells (count of d_list)
+  int* d_list = nullptr;        // the running cells in order (batch_check_kernel)
   std::vector<CellStatus> status_host;
   // layout offsets
   size_t off_buf[2] = {0, 0}, off_flags = 0, off_cls = 0, off_slot = 0, off_coef = 0, off_part = 0,
          off_part2 = 0, off_res = 0, off_stage = 0, off_cells = 0, off_active = 0,
-         off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, off_side[2] = {0, 0},
+         off_active_all = 0, off_status = 0, off_results = 0, off_nactive = 0, off_list = 0,
+         off_side[2] = {0, 0},
          side_bytes = 0, total = 0;
 };
 
@@ -161,7 +163,7 @@ int step_nbx(lbm_domain d) {
 dim3 step_block(lbm_domain d) { return dim3(64, d->waves, 1); }
 dim3 step_grid(lbm_domain d) {
   const int nby = (d->tiling.nty + d->rows - 1) / d->rows;
-  return dim3(step_nbx(d) * nby, 1, d->geo.nz);
+  return dim3(step_nbx(d), nby, d->geo.nz);
 }
 
 // Non-temporal stores pay once the two state buffers are well beyond the
@@ -188,6 +190,11 @@ void layout(lbm_domain d) {
   // lane; 128^3, in the cache: 36 us against 34 us, so not there), one
   // domain (batches step one cell per lane), the box's x edge on a tile edge
   d->pairs = d->elem == 2 && d->streaming && !d->batch && d->geo.nx % (1 << tw) == 0;
+  // FP32 and FP64 states of one domain are cut into runs of 128 addresses:
+  // every z plane starts on a run (the step kernels split an address into a
+  // wavefront-uniform plane part and a 32-bit in-plane part), so a plane of
+  // an odd number of tiles gets one tile of padding
+  if (d->elem != 2 && !d->batch && d->tiling.plane % (1 << kStepRunLog2)) d->tiling.plane += 64;
   d->cell_addrs = (long long)d->tiling.plane * d->geo.nz_cell;
   d->naddr = (long long)d->tiling.plane * d->geo.nz;
   const int64_t n = d->naddr;
@@ -202,7 +209,7 @@ void layout(lbm_domain d) {
     d->tiling.run_pitch = ((n + 1023) / 1024) * 1024 + 512;
     d->state_elems = (long long)kQ * d->tiling.run_pitch;
   } else {
-    d->tiling.run_log2 = d->batch ? 6 : 7;
+    d->tiling.run_log2 = d->batch ? kBatchRunLog2 : kStepRunLog2;
     d->tiling.run_pitch = 1LL << d->tiling.run_log2;
     const long long run = d->tiling.run_pitch;
     d->state_elems = (long long)kQ * ((n + run - 1) / run * run);
@@ -267,6 +274,8 @@ void layout(lbm_domain d) {
   o += align256(nb * kRedVals * sizeof(double));
   d->off_nactive = o;
   o += align256(sizeof(int));
+  d->off_list = o;
+  o += align256(nb * sizeof(int));
   // IEBB on one domain: 4 values of the compute type per address and state
   d->side_bytes = uses_side(d) ? (size_t)n * 4 * (d->elem == 8 ? 8 : 4) : 0;
   for (int i = 0; i < 2; ++i) {
@@ -276,8 +285,31 @@ void layout(lbm_domain d) {
   d->total = o;
 }
 
+// The in-plane part of a state byte offset (state_lane) fits in 32 bits.
+bool plane_offsets_fit(lbm_domain d) {
+  const int64_t per_address = d->elem == 2 ? 2 : (int64_t)kQ * d->elem;
+  return per_address * d->tiling.plane < (int64_t(1) << 32);
+}
+
 // Cells of one z period in row-major host order (one batch cell, or the box).
 long long cell_cells(lbm_domain d) { return (long long)d->geo.nx * d->geo.ny * d->geo.nz_cell; }
+
+// The FP32 copies of a StepParams' rates and jumps, and the 16-bit formats'
+// factors between stored values h and deviations g (h = sigma g / w_k) per
+// weight class.
+void set_float_params(StepParams& sp) {
+  const double w[3] = {kLat.w[0], kLat.w[1], kLat.w[7]};
+  for (int i = 0; i < 3; ++i) {
+    sp.dec[i] = (float)(w[i] * (1.0 / sp.sigma));
+    sp.enc[i] = (float)(sp.sigma / w[i]);
+  }
+  sp.omega_pf = (float)sp.omega_p;
+  sp.omega_mf = (float)sp.omega_m;
+  sp.s_ef = (float)sp.s_e;
+  sp.s_zetaf = (float)sp.s_zeta;
+  sp.jump_axisf = (float)sp.jump_axis;
+  sp.jump_diagf = (float)sp.jump_diag;
+}
 
 StepParams step_params(lbm_domain d) {
   StepParams sp;
@@ -292,6 +324,7 @@ StepParams step_params(lbm_domain d) {
   sp.s_e = d->s_e;
   sp.s_zeta = d->s_zeta;
   sp.sigma = d->sigma;
+  set_float_params(sp);
   sp.wall = d->p.wall;
   sp.solid_writes = d->solid_writes;
   sp.side_in = d->side[d->cur];
@@ -408,10 +441,13 @@ lbm_status enqueue_steps(lbm_domain d, int64_t n) {
 // ---- batches
 
 dim3 batch_block(lbm_domain d) { return dim3(64, d->bby, 1); }
-dim3 batch_grid(lbm_domain d) {
+// Grid over `slots` cells (all of them by default): tile blocks times z
+// blocks of each cell.
+dim3 batch_grid(lbm_domain d, int slots = -1) {
   const int tiles = d->tiling.ntx * d->tiling.nty;
+  if (slots < 0) slots = d->batch;
   return dim3((tiles + d->bby - 1) / d->bby, 1,
-              (unsigned)((long long)d->batch * d->geo.nz_cell / d->zper));
+              (unsigned)((long long)slots * d->geo.nz_cell / d->zper));
 }
 
 const void* batch_function(lbm_domain d, bool red) {
@@ -429,18 +465,23 @@ struct BatchArgs {
   const uint32_t* flags;
   const StepParams* cells;
   const int* active;
+  const int* list;
+  const int* n_list;
   int nz_cell;
   long long cell_size;
   int zper;
   double* partials;
-  void* ptrs[10];
-  void fill(lbm_domain d, int from, const int* act) {
+  void* ptrs[12];
+  // listed: the grid runs over d_list's cells (batch runs), else over all
+  void fill(lbm_domain d, int from, const int* act, bool listed) {
     src = d->buf[from];
     dst = d->buf[1 - from];
     cls = d->cls;
     flags = d->flags;
     cells = d->d_cells;
     active = act;
+    list = listed ? d->d_list : nullptr;
+    n_list = listed ? d->d_nactive : nullptr;
     nz_cell = d->geo.nz_cell;
     cell_size = d->cell_addrs;
     zper = d->zper;
@@ -451,16 +492,18 @@ struct BatchArgs {
     ptrs[3] = &flags;
     ptrs[4] = &cells;
     ptrs[5] = &active;
-    ptrs[6] = &nz_cell;
-    ptrs[7] = &cell_size;
-    ptrs[8] = &zper;
-    ptrs[9] = &partials;
+    ptrs[6] = &list;
+    ptrs[7] = &n_list;
+    ptrs[8] = &nz_cell;
+    ptrs[9] = &cell_size;
+    ptrs[10] = &zper;
+    ptrs[11] = &partials;
   }
 };
 
 lbm_status launch_batch_step(lbm_domain d, bool red, const int* act) {
   BatchArgs a;
-  a.fill(d, d->cur, act);
+  a.fill(d, d->cur, act, false);
   HIP_OK(d, hipLaunchKernel(batch_function(d, red), batch_grid(d), batch_block(d), a.ptrs, 0,
                             d->stream));
   d->cur = 1 - d->cur;
@@ -479,9 +522,10 @@ lbm_status enqueue_batch_steps(lbm_domain d, int64_t n) {
 
 // Graph of `reps` check intervals of `interval` steps starting from buffer
 // `from`: (interval - 1) steps, one step with block partials, the per-cell
-// fold and the device-side convergence test.  Kernel nodes only.
+// fold and the device-side convergence test.  Kernel nodes only.  The steps
+// run over `slots` entries of the list of running cells.
 lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, double tol,
-                             long long max_steps, hipGraphExec_t* out) {
+                             long long max_steps, int slots, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIP_OK(d, hipGraphCreate(&g, 0));
   hipGraphNode_t prev = nullptr;
@@ -498,7 +542,7 @@ lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, dou
     if (e == hipSuccess) prev = node;
     return e;
   };
-  const dim3 grid = batch_grid(d), block = batch_block(d);
+  const dim3 grid = batch_grid(d, slots), block = batch_block(d);
   const long long blocks_per_cell =
       (long long)grid.x * grid.y * ((long long)d->geo.nz_cell / d->zper);  // grid.y is 1
   int parity = from;
@@ -507,7 +551,7 @@ lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, dou
     for (int i = 0; i < interval && e == hipSuccess; ++i) {
       const bool red = i == interval - 1;
       BatchArgs a;
-      a.fill(d, parity, d->d_active);
+      a.fill(d, parity, d->d_active, true);
       e = add(batch_function(d, red), grid, block, a.ptrs);
       parity = 1 - parity;
     }
@@ -522,6 +566,7 @@ lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, dou
     const double* resc = d->d_results;
     CellStatus* st = d->d_status;
     int* actw = d->d_active;
+    int* lst = d->d_list;
     int* nact = d->d_nactive;
     int ncells = d->batch;
     double inv = 1.0 / (double)d->cell_size;
@@ -529,8 +574,8 @@ lbm_status build_batch_graph(lbm_domain d, int from, int reps, int interval, dou
     long long ms = max_steps;
     int iv = interval;
     int pn = parity;
-    void* cargs[] = {(void*)&resc, (void*)&st,  (void*)&actw, (void*)&nact, (void*)&ncells,
-                     (void*)&inv,  (void*)&t,   (void*)&ms,   (void*)&iv,   (void*)&pn};
+    void* cargs[] = {(void*)&resc, (void*)&st, (void*)&actw, (void*)&lst, (void*)&nact,
+                     (void*)&ncells, (void*)&inv, (void*)&t, (void*)&ms, (void*)&iv, (void*)&pn};
     e = add((const void*)batch_check_kernel, dim3(1), dim3(1024), cargs);
   }
   if (e != hipSuccess) {
@@ -578,6 +623,7 @@ lbm_status upload_cell_params(lbm_domain d) {
     sp.s_e = 1.0 / (0.5 + (c.tau - 0.5) / 4.6);
     sp.s_zeta = 8.0 * (2.0 - sp.omega_p) / (8.0 - sp.omega_p);
     sp.sigma = 1.0;
+    set_float_params(sp);
     sp.seed = 0;
     sp.wall = d->p.wall;
     sp.solid_writes = d->solid_writes;
@@ -592,19 +638,32 @@ lbm_status batch_run(lbm_domain d, double tol, int64_t max_steps, int64_t* steps
                      double* residual) {
   const int m = d->p.check_interval;
   const int reps = std::max(1, 512 / m);
-  batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_status, d->d_active,
-                                                                    d->batch, d->cur);
+  batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(
+      d->d_status, d->d_active, d->d_list, d->d_nactive, d->batch, d->cur);
   HIP_OK(d, hipGetLastError());
-  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  // Graphs by slot count: all cells, then the next power of two at or above
+  // the running count read after each replay (the device list holds the
+  // running cells, so the launch shrinks as cells stop; 256 cells of 64^3,
+  // two of them run to the step limit: 71.8 -> 64.7 s for the run, whose
+  // last 170k steps have few cells running).  Index: log2 of the slots (the
+  // last one for all cells) and buffer parity.
+  constexpr int kSlotGraphs = 32;
+  hipGraphExec_t ex[kSlotGraphs][2] = {};
   lbm_status st = LBM_OK;
   int64_t done = 0;
   int nact = d->batch;
   while (done < max_steps && nact > 0) {
-    if (!ex[d->cur]) {
-      st = build_batch_graph(d, d->cur, reps, m, tol, (long long)max_steps, &ex[d->cur]);
+    int lg = 0;
+    while ((1LL << lg) < nact) ++lg;
+    const bool all = (1LL << lg) >= d->batch;
+    const int slots = all ? d->batch : (1 << lg);
+    const int gi = all ? kSlotGraphs - 1 : lg;
+    hipGraphExec_t& g = ex[gi][d->cur];
+    if (!g) {
+      st = build_batch_graph(d, d->cur, reps, m, tol, (long long)max_steps, slots, &g);
       if (st != LBM_OK) break;
     }
-    hipError_t e = hipGraphLaunch(ex[d->cur], d->stream);
+    hipError_t e = hipGraphLaunch(g, d->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(&nact, d->d_nactive, sizeof(int), hipMemcpyDeviceToHost, d->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
@@ -618,8 +677,9 @@ lbm_status batch_run(lbm_domain d, double tol, int64_t max_steps, int64_t* steps
     d->step_count += n;
     report_progress(d, done, nact);
   }
-  for (int i = 0; i < 2; ++i)
-    if (ex[i]) (void)hipGraphExecDestroy(ex[i]);
+  for (auto& pair : ex)
+    for (hipGraphExec_t g : pair)
+      if (g) (void)hipGraphExecDestroy(g);
   if (st != LBM_OK) return st;
   // every cell's final state into buffer cur
   if (d->p.storage == LBM_FP64)
@@ -836,6 +896,10 @@ LBM_API lbm_status lbm_create_domain(const uint8_t* solid_mask, const lbm_sphere
     delete d;
     return bad("nx*ny*nz (padded to whole tiles) must be below 2^31");
   }
+  if (!plane_offsets_fit(d)) {
+    delete d;
+    return bad("nx*ny (padded to whole tiles) must be below 2^32 / (19 * value bytes)");
+  }
   choose_sigma(d, 0.0);
   *out = d;
   return LBM_OK;
@@ -913,13 +977,14 @@ LBM_API lbm_status lbm_bind(lbm_domain d, void* workspace, size_t bytes, void* s
   d->d_status = (CellStatus*)(d->ws + d->off_status);
   d->d_results = (double*)(d->ws + d->off_results);
   d->d_nactive = (int*)(d->ws + d->off_nactive);
+  d->d_list = (int*)(d->ws + d->off_list);
   for (int i = 0; i < 2; ++i) d->side[i] = d->side_bytes ? d->ws + d->off_side[i] : nullptr;
   if (d->batch) {
     lbm_status bst = upload_cell_params(d);
     if (bst != LBM_OK) return bst;
     fill_int_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_active_all, d->batch, 1);
-    batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(d->d_status, d->d_active,
-                                                                      d->batch, 0);
+    batch_reset_kernel<<<(d->batch + 255) / 256, 256, 0, d->stream>>>(
+        d->d_status, d->d_active, d->d_list, d->d_nactive, d->batch, 0);
   }
 
   // flag words and class bytes in tiled order (padding: solid)
@@ -1442,6 +1507,10 @@ LBM_API lbm_status lbm_create_batch(int32_t n_cells, const uint8_t* masks,
   if (d->naddr >= (int64_t(1) << 31)) {
     delete d;
     return bad("n_cells*nx*ny*nz (padded to whole tiles) must be below 2^31");
+  }
+  if (!plane_offsets_fit(d)) {
+    delete d;
+    return bad("nx*ny (padded to whole tiles) must be below 2^32 / (19 * value bytes)");
   }
   choose_sigma(d, 0.0);
   *out = d;

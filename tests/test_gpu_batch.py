@@ -84,6 +84,32 @@ def test_batch_run_to_residual_per_cell(orc):
     b.close()
 
 
+def test_batch_run_shrinks_to_running_cells():
+    """As cells stop, a run launches blocks for the running cells only (the
+    device-side list of running cells, graphs sized to the next power of two
+    at or above their count): every cell's status, stopping step and final
+    state equal those of the same cell run alone, bit for bit, also for cells
+    listed behind stopped ones."""
+    shape = (16, 16, 16)
+    rng = np.random.default_rng(12)
+    cells = [dict(spheres=inputs.random_spheres(shape, 2, (2.0, 4.0), seed=120 + i),
+                  tau=float(t), magic=3 / 16, delta_rho=float(rng.uniform(0.5, 1.5) * 1e-5))
+             for i, t in enumerate([1.5, 0.7, 1.2, 0.9, 1.4, 0.8])]
+    b = lbm.Batch(shape, cells, wall="cli", storage="fp64", check_interval=20)
+    b.run_to_residual(1e-6, 20000)
+    r = b.results()
+    g = b.get_state()
+    b.close()
+    assert len(set(r["steps"].tolist())) >= 4
+    for i, c in enumerate(cells):
+        b1 = lbm.Batch(shape, [c], wall="cli", storage="fp64", check_interval=20)
+        b1.run_to_residual(1e-6, 20000)
+        r1 = b1.results()
+        assert r1["status"][0] == r["status"][i] and r1["steps"][0] == r["steps"][i], i
+        assert np.array_equal(b1.get_state()[:, 0], g[:, i]), i
+        b1.close()
+
+
 def test_batch_residual_with_largest_workgroups(orc):
     """Regression test of the per-block FP64 reduction at the largest batch
     workgroup (16 wavefronts, 1024 threads, every wavefront holding fluid
