@@ -133,7 +133,8 @@ typedef struct {
   int64_t bytes_per_fluid_update; /* algorithmic HBM bytes per fluid-cell update */
   double storage_scale;    /* sigma of 16-bit storage (1 otherwise)             */
   int32_t tile_width;      /* cells: the device buffers' tiles (x extent)       */
-  int32_t tile_height;     /* cells: the tiles' y extent (width * height = 64)  */
+  int32_t tile_height;     /* cells: the tiles' y extent (width * height = 64   */
+                           /* or 128)                                           */
 } lbm_info;
 
 /* Create a domain on the host (no device work).  Sec. 3 / Sec. 2.2.1.

@@ -50,24 +50,25 @@ enum { kRuleSBB = 0, kRuleCLI = 1, kRuleLIBB = 2, kRuleQIBB = 3, kRuleIEBB = 4, 
 // never read as a neighbour (the periodic wrap uses nx and ny).
 struct Tiling {
   int nx, ny;            // box edge in x and y (cells)
-  int tw_log2, th_log2;  // tile width and height, log2 (sum 6)
+  int tw_log2, th_log2;  // tile width and height, log2 (sum 6 or 7: tiles of 64 or 128 cells)
   int ntx;               // tiles per tile row (padded nx / tile width)
   int nty;               // tile rows per plane
-  int plane;             // cells per z plane including padding: ntx * nty * 64
+  int plane;             // cells per z plane including padding: ntx * nty * tile cells
   int run_log2;          // state buffers: runs of 2^run_log2 consecutive addresses,
   long long run_pitch;   // ... each direction of a run run_pitch elements after the last
+  __host__ __device__ int tile_log2() const { return tw_log2 + th_log2; }
   __host__ __device__ int xpart(int x) const {
-    return ((x >> tw_log2) << 6) | (x & ((1 << tw_log2) - 1));
+    return ((x >> tw_log2) << tile_log2()) | (x & ((1 << tw_log2) - 1));
   }
   __host__ __device__ int ypart(int y) const {
-    return (y >> th_log2) * (ntx << 6) + ((y & ((1 << th_log2) - 1)) << tw_log2);
+    return (y >> th_log2) * (ntx << tile_log2()) + ((y & ((1 << th_log2) - 1)) << tw_log2);
   }
   __host__ __device__ int at(int x, int y, int z) const { return xpart(x) + ypart(y) + z * plane; }
   // inverse of at() (padding cells give x >= nx or y >= ny)
   __host__ __device__ void coords(int a, int& x, int& y, int& z) const {
     z = a / plane;
     const int r = a - z * plane;
-    const int t = r >> 6, l = r & 63;
+    const int t = r >> tile_log2(), l = r & ((1 << tile_log2()) - 1);
     x = ((t % ntx) << tw_log2) + (l & ((1 << tw_log2) - 1));
     y = ((t / ntx) << th_log2) + (l >> tw_log2);
   }
@@ -1018,8 +1019,9 @@ __device__ __forceinline__ void store_side(const StepParams& p, uint8_t cls, int
 // Cell of this thread in plane z: wavefront threadIdx.y of the block takes
 // tile blockIdx.x * blockDim.y + threadIdx.y of the plane (tiles in row-major
 // order), lane threadIdx.x its cell in the tile, so the lanes of a wavefront
-// hold 64 consecutive addresses.  inside is false for padding cells and for
-// tiles past the end of the plane (c must not be used then).
+// hold 64 consecutive addresses (tiles of 64 cells: batches).  inside is
+// false for padding cells and for tiles past the end of the plane (c must
+// not be used then).
 struct TileCell {
   int x, y, c;  // coordinates and address
   int r;        // address within the z plane
@@ -1053,17 +1055,21 @@ __device__ __forceinline__ long long step_block_id() {
   return blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
 }
 
-// tile_cell for the single-domain step: the tile is the wavefront's unit.
+// tile_cell for the single-domain step: the wavefront's unit is 64
+// consecutive addresses of its tile row (a tile of 64 cells, or half of one
+// of 128).
 __device__ __forceinline__ TileCell step_tile_cell(const StepParams& p, int z) {
   const Tiling& t = p.t;
-  int tx, ty;
-  step_unit(p, tx, ty);
-  const int l = threadIdx.x;
+  int u, ty;
+  step_unit(p, u, ty);
+  const int tl = t.tile_log2();
+  const int q = (u << 6) + threadIdx.x;  // address within the tile row
+  const int tx = q >> tl, o = q & ((1 << tl) - 1);
   TileCell r;
-  r.x = (tx << t.tw_log2) + (l & ((1 << t.tw_log2) - 1));
-  r.y = (ty << t.th_log2) + (l >> t.tw_log2);
+  r.x = (tx << t.tw_log2) + (o & ((1 << t.tw_log2) - 1));
+  r.y = (ty << t.th_log2) + (o >> t.tw_log2);
   r.inside = tx < t.ntx && ty < t.nty && r.x < t.nx && r.y < t.ny;
-  r.r = ((ty * t.ntx + tx) << 6) + l;
+  r.r = ty * (t.ntx << tl) + q;
   r.c = r.r + z * t.plane;
   return r;
 }
@@ -1135,7 +1141,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
 // and even at the full 8 wavefronts per SIMD too few bytes are in flight to
 // keep HBM busy (all-fluid 512^3 box: 0.50 of 8 TB/s against 0.64 for FP32).
 // Here each lane takes the two x-adjacent cells of one aligned 4-byte word:
-// a wavefront covers the 128 consecutive addresses of two tiles and loads 256
+// a wavefront covers 128 consecutive addresses (a 32 x 4 tile) and loads 256
 // bytes per direction.  A pull with e_x = 0 reads the word at the cells' own
 // x; with e_x = +1 cell A (even x) needs the high half of the word to its
 // left, which is the next lower lane's word (a DPP row shift) except at the
@@ -1144,12 +1150,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const S* __restrict_
 // (nx a multiple of the tile width), so the periodic wrap only happens at the
 // reads at tile edges.  A lane whose pair holds one solid cell stores that
 // cell's own (unchanged) values with the fluid one.  Every cell goes through
-// finish_node with its own address, so the stored results are the one-cell
-// kernel's.
+// finish_values with its own coordinates and is rounded with its own random
+// word, so the stored results are the one-cell kernel's.
 
 // In-plane address of a pair wavefront's cell A and its coordinates.  The
-// wavefront's unit u is the tiles 2u and 2u + 1 of its tile row (lanes 0-31
-// and 32-63), 128 consecutive addresses when both exist.
+// wavefront's unit u is the 128 consecutive addresses [128u, 128u + 128) of
+// its tile row: one 32 x 4 tile (the layout of 16-bit states beyond 1 GiB),
+// or two x-adjacent tiles of 64 cells (lanes 0-31 and 32-63).
 struct PairCell {
   int a;             // in-plane address of cell A (even); cell B is a + 1
   int x, y;          // cell A (cell B is x + 1)
@@ -1162,11 +1169,12 @@ __device__ __forceinline__ PairCell pair_cell(const StepParams& p) {
   int u, ty;
   step_unit(p, u, ty);
   const int l = threadIdx.x;
-  const int tx = 2 * u + (l >> 5);
-  const int o = (2 * l) & 63;
+  const int tl = t.tile_log2();
+  const int q = (u << 7) + 2 * l;  // address within the tile row
+  const int tx = q >> tl, o = q & ((1 << tl) - 1);
   const int xin = o & ((1 << t.tw_log2) - 1);
   PairCell r;
-  r.a = ((ty * t.ntx + tx) << 6) + o;
+  r.a = ty * (t.ntx << tl) + q;
   r.x = (tx << t.tw_log2) + xin;
   r.y = (ty << t.th_log2) + (o >> t.tw_log2);
   r.inside = tx < t.ntx && ty < t.nty && r.y < t.ny;

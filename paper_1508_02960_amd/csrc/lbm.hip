@@ -133,20 +133,21 @@ double pick_sigma(double m) {
   return std::ldexp(1.0, (int)std::floor(std::log2(kScaleTarget / m)));
 }
 
-// Tiles of 64 cells, 2^tw_log2 wide.  Compact tiles for states beyond the
-// last-level cache (512^3 sphere pack, FP32 CLI: 16 x 4 tiles 2.51 ms per
-// step against 2.56 ms for 8 x 8 tiles and 2.98 ms for rows); 64 x 1 tiles
-// (rows) for smaller states, which stay largely in the 256 MB cache and
-// where rows step fastest (128^3, FP32: 54 us against 62 us for 16 x 4).
-Tiling make_tiling(int nx, int ny, int tw_log2) {
+// Tiles of 2^tile_log2 cells (64 or 128), 2^tw_log2 wide.  Compact tiles
+// for states beyond the last-level cache (512^3 sphere pack, FP32 CLI: 16 x 4
+// tiles 2.51 ms per step against 2.56 ms for 8 x 8 tiles and 2.98 ms for
+// rows); 64 x 1 tiles (rows) for smaller states, which stay largely in the
+// 256 MB cache and where rows step fastest (128^3, FP32: 54 us against 62 us
+// for 16 x 4).
+Tiling make_tiling(int nx, int ny, int tw_log2, int tile_log2) {
   Tiling t{};
   t.nx = nx;
   t.ny = ny;
   t.tw_log2 = tw_log2;
-  t.th_log2 = 6 - t.tw_log2;
+  t.th_log2 = tile_log2 - t.tw_log2;
   t.ntx = (nx + (1 << t.tw_log2) - 1) >> t.tw_log2;
   t.nty = (ny + (1 << t.th_log2) - 1) >> t.th_log2;
-  t.plane = t.ntx * t.nty * 64;
+  t.plane = (t.ntx * t.nty) << tile_log2;
   return t;
 }
 
@@ -154,7 +155,8 @@ Tiling make_tiling(int nx, int ny, int tw_log2) {
 // one z plane; a wavefront takes a unit of a tile row (one tile, or two
 // x-adjacent tiles with two cells per lane).
 int step_units_per_row(lbm_domain d) {
-  return d->pairs ? (d->tiling.ntx + 1) / 2 : d->tiling.ntx;
+  const int row = d->tiling.ntx << d->tiling.tile_log2();  // addresses per tile row
+  return d->pairs ? (row + 127) / 128 : row / 64;
 }
 int step_nbx(lbm_domain d) {
   const int bw = d->waves / d->rows;
@@ -181,15 +183,21 @@ void layout(lbm_domain d) {
   // large states: compact tiles and streaming stores (sizes estimated on the
   // unpadded cell count; padding adds at most a few percent)
   d->streaming = 2 * (size_t)kQ * (size_t)d->geo.ncell * d->elem > kStreamingBytes;
-  // compact tiles: 16 x 4, or 32 x 2 for the two-cell lanes of the 16-bit
-  // formats (a 16-lane DPP row is then one tile row)
+  // compact tiles 16 x 4; the 16-bit formats' tiles are 32 cells wide (a
+  // 16-lane DPP row of the two-cell lanes is then one tile row)
   const int tw = d->streaming ? (d->elem == 2 ? 5 : 4) : 6;
-  d->tiling = make_tiling(d->geo.nx, d->geo.ny, tw);
   // two cells per lane: 16-bit storage beyond the last-level cache (512^3
   // sphere pack, FP16: 1.68 ms per step against 1.73 ms for one cell per
   // lane; 128^3, in the cache: 36 us against 34 us, so not there), one
   // domain (batches step one cell per lane), the box's x edge on a tile edge
-  d->pairs = d->elem == 2 && d->streaming && !d->batch && d->geo.nx % (1 << tw) == 0;
+  const bool pairs = d->elem == 2 && d->streaming && !d->batch && d->geo.nx % (1 << tw) == 0;
+  // then tiles of 32 x 4 cells, one per wavefront: a +-y pull shares its
+  // tile's lines except for one row in four, against one in two for 32 x 2
+  // tiles (512^3 sphere pack, FP16: 1.54 ms per step with 4 wavefronts per
+  // workgroup against 1.58 ms for pairs of 32 x 2 tiles; all fluid 2.02
+  // against 2.17 ms; 32 x 8 tiles 1.79 and 1.95 ms)
+  d->tiling = make_tiling(d->geo.nx, d->geo.ny, tw, pairs ? 7 : 6);
+  d->pairs = pairs;
   // FP32 and FP64 states of one domain are cut into runs of 128 addresses:
   // every z plane starts on a run (the step kernels split an address into a
   // wavefront-uniform plane part and a 32-bit in-plane part), so a plane of
@@ -214,10 +222,10 @@ void layout(lbm_domain d) {
     const long long run = d->tiling.run_pitch;
     d->state_elems = (long long)kQ * ((n + run - 1) / run * run);
   }
-  // 8 wavefronts (16 x 4 tiles: 128 x 4 cells) with compact tiles, 2 with
-  // two cells per lane (32 x 8 cells), 4 (256 cells of a row) with rows;
-  // never more than a plane has work for
-  d->waves = d->streaming ? (d->pairs ? 2 : 8) : 4;
+  // 8 wavefronts (16 x 4 tiles: 128 x 4 cells) with compact tiles, 4 with
+  // two cells per lane (32 x 4 tiles: 128 x 4 cells), 4 (256 cells of a row)
+  // with rows; never more than a plane has work for
+  d->waves = d->streaming ? (d->pairs ? 4 : 8) : 4;
   const int units = step_units_per_row(d);
   d->rows = 1;
   while (d->waves / d->rows > units && d->rows < d->tiling.nty) d->rows *= 2;
@@ -241,7 +249,7 @@ void layout(lbm_domain d) {
   // partial sums: room for the step shapes of lbm_set_step_shape with at
   // least two wavefronts per workgroup (about tiles / 2 blocks per plane)
   const dim3 sg = step_grid(d);
-  const long long half_row = (d->tiling.ntx + 1) / 2;
+  const long long half_row = ((d->tiling.ntx << (d->tiling.tile_log2() - 6)) + 1) / 2;
   d->n_partials = std::max<long long>(kRedBlocks, (long long)sg.x * sg.y * sg.z);
   d->n_partials =
       std::max<long long>(d->n_partials, half_row * d->tiling.nty * (long long)d->geo.nz);

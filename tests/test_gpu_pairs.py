@@ -82,13 +82,14 @@ def test_pair_kernel_residual_checks():
 
 
 def test_pair_kernel_large_state_tiles():
-    """A state beyond 1 GiB uses 32 x 2 tiles and non-temporal stores; ny odd
-    leaves a padding row in the last tile row."""
+    """A state beyond 1 GiB uses 32 x 4 tiles (one per wavefront) and
+    non-temporal stores; ny = 255 leaves a padding row in the last tile row.
+    The one-cell kernel takes half a tile per wavefront there."""
     shape = (224, 255, 256)
     kw = dict(tau=0.6, magic=3 / 16, delta_rho=1e-3, collision="trt", wall="cli",
               spheres=inputs.random_spheres(shape, 40, (8.0, 30.0), seed=43))
     d = lbm.Domain(shape, storage="fp16", bind=False, **kw)
-    assert (d.info.tile_width, d.info.tile_height) == (32, 2)
+    assert (d.info.tile_width, d.info.tile_height) == (32, 4)
     d.close()
     (a, b), _ = _pair_and_single(shape, "fp16", 4, large=True, **kw)
     assert np.array_equal(a, b)
@@ -137,6 +138,31 @@ def test_pair_shape_rejected_where_it_cannot_run():
         d.set_step_shape(3, 1, False)  # waves not a power of two
     with pytest.raises(lbm.LbmError):
         d.set_step_shape(4, 3, False)  # rows must divide waves
+    d.close()
+
+
+def test_pair_kernel_matches_oracle_on_large_state_tiles(orc):
+    """One step of a state beyond 1 GiB (32 x 4 tiles, a padding row in the
+    last tile row, streaming stores) from the state the GPU holds, against
+    the FP64 oracle: within one spacing of the format plus half a spacing of
+    the stored CLI coefficient, as on the small boxes."""
+    spacing = 2.0 ** -10
+    shape = (256, 250, 224)
+    sp = inputs.random_spheres(shape, 30, (8.0, 24.0), seed=49)
+    kw = dict(tau=0.7, magic=0.21, delta_rho=3e-3, collision="trt", wall="cli", spheres=sp)
+    d = lbm.Domain(shape, storage="fp16", **kw)
+    assert (d.info.tile_width, d.info.tile_height) == (32, 4) and d.step_shape()[2]
+    d.set_state(inputs.random_populations(shape, 1e-3, seed=50))
+    g_held = d.get_state()
+    o = orc.Oracle(shape, **kw)
+    o.set_state(g_held)
+    del g_held
+    o.step(1)
+    d.step(1)
+    fluid = o.mask == 0
+    got = d.get_state()
+    r = float(np.max(np.abs(got[..., fluid] - o.g[..., fluid])) / np.max(np.abs(o.g[..., fluid])))
+    assert r < 2 * spacing + 1e-5, r
     d.close()
 
 
