@@ -867,9 +867,10 @@ __device__ __forceinline__ void finish_node(typename ComputeOf<S>::type (&g)[kQ]
 // there).  SPLIT selects pulls from scalar per-direction bases plus 32-bit
 // lane offsets (state_at); without it every lane forms 64-bit addresses.
 // The split form needs about 40 more scalar registers; in the kernels with
-// the general wall rules and in the batch kernel it made the compiler spill
-// scalar registers (general rules 5-11% slower at 512^3, batches 6%), so only
-// the single-domain SBB / CLI kernels use it.
+// the general wall rules it made the compiler spill scalar registers (5-11%
+// slower at 512^3), and the batch kernel, whose cell base comes from a table,
+// got no scalar-base loads from it and was 1% slower, so only the
+// single-domain SBB / CLI kernels use it.
 template <typename S, int COLL, int WALL, bool SPLIT>
 __device__ __forceinline__ void update_node(const S* __restrict__ src, S (&out)[kQ],
                                             const uint32_t* __restrict__ flags,
