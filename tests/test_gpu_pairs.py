@@ -166,6 +166,30 @@ def test_pair_kernel_matches_oracle_on_large_state_tiles(orc):
     d.close()
 
 
+def test_one_cell_kernel_on_large_state_without_pairs(orc):
+    """A 16-bit state beyond 1 GiB whose nx (200) is not a multiple of the
+    32-cell tiles: one cell per lane on 32 x 2 tiles with a padded last
+    tile per row and streaming stores; one step against the FP64 oracle."""
+    spacing = 2.0 ** -10
+    shape = (280, 256, 200)
+    sp = inputs.random_spheres(shape, 30, (8.0, 24.0), seed=51)
+    kw = dict(tau=0.7, magic=0.21, delta_rho=3e-3, collision="trt", wall="cli", spheres=sp)
+    d = lbm.Domain(shape, storage="fp16", **kw)
+    assert (d.info.tile_width, d.info.tile_height) == (32, 2) and not d.step_shape()[2]
+    d.set_state(inputs.random_populations(shape, 1e-3, seed=52))
+    g_held = d.get_state()
+    o = orc.Oracle(shape, **kw)
+    o.set_state(g_held)
+    del g_held
+    o.step(1)
+    d.step(1)
+    fluid = o.mask == 0
+    got = d.get_state()
+    r = float(np.max(np.abs(got[..., fluid] - o.g[..., fluid])) / np.max(np.abs(o.g[..., fluid])))
+    assert r < 2 * spacing + 1e-5, r
+    d.close()
+
+
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
 def test_pair_kernel_matches_oracle(orc, storage):
     """One step of the pair kernel from the state the GPU holds, stepped by

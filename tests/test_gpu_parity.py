@@ -187,14 +187,15 @@ def test_bench_configuration_fp32(orc):
 
 
 @pytest.mark.parametrize("storage,shape,tol", [("fp32", (180, 196, 208), 1e-5),
+                                               ("fp32", (184, 196, 200), 1e-5),
                                                ("fp64", (320, 100, 112), 1e-12)])
 def test_streaming_layout_with_padded_planes(orc, storage, shape, tol):
     """States beyond 1 GiB: 16 x 4 tiles, runs of 128 addresses and streaming
     stores.  A plane of an odd number of tiles (13 x 49, 7 x 25) gets one
     padding tile, so that every z plane starts on a run (the step kernel
-    splits addresses into a plane part and a 32-bit in-plane part).
-    Full-field velocity after 3 steps from a perturbed equilibrium, against
-    the oracle."""
+    splits addresses into a plane part and a 32-bit in-plane part); nx = 200
+    also pads the last tile of each row.  Full-field velocity after 3 steps
+    from a perturbed equilibrium, against the oracle."""
     sp = inputs.random_spheres(shape, 12, (8.0, 20.0), seed=47)
     o, d = _pair(orc, shape, storage=storage, tau=0.8, magic=3 / 16, delta_rho=1e-4,
                  collision="trt", wall="cli", spheres=sp)
