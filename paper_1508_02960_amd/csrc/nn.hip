@@ -663,6 +663,93 @@ __global__ __launch_bounds__(256) void bias_grad_part_kernel(const float* __rest
 
 constexpr int kBiasSplits = 512;
 
+// Bias-gradient partial sums with four consecutive channels per thread (c a
+// multiple of 4, at most 1024): thread (g, q) of a block sums channels
+// 4q..4q+3 over the block's voxels v = beg + g, beg + g + G, ... (G = 256 /
+// (c / 4) voxel groups), then the block adds the G partial sums in order.
+// Both nn_bias_grad (dz given, FUSED false) and nn_relu_backward_bias (dz =
+// relu'(a) da, stored as BF16, FUSED true) sum in this order, so their db
+// agree bit for bit.  vec selects 16-byte FP32 and 8-byte BF16 accesses when
+// the pointers allow them (the order is the same either way).  Against one
+// channel per thread with 4-byte loads, whose 512 workgroups waited on each
+// load in turn: 158 -> 73 us for the largest layer of a 64^3 x 4 training
+// step (81 -> 35 us on average).
+template <bool FUSED>
+__global__ __launch_bounds__(256) void bias4_part_kernel(const float* __restrict__ da,
+                                                         const uint16_t* __restrict__ a,
+                                                         uint16_t* __restrict__ dzb,
+                                                         float* __restrict__ part, long long m,
+                                                         int c, long long per, int relu, int vec) {
+  __shared__ float4 sh[256];
+  const int c4 = c >> 2;
+  const int G = 256 / c4;
+  const int tid = threadIdx.x, g = tid / c4, q = tid - g * c4;
+  const long long beg = (long long)blockIdx.x * per;
+  const long long end = beg + per < m ? beg + per : m;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (g < G) {
+#pragma unroll 4
+    for (long long v = beg + g; v < end; v += G) {
+      const long long i = v * c + 4 * q;
+      float z[4];
+      if (vec) {
+        const float4 t = *reinterpret_cast<const float4*>(da + i);
+        z[0] = t.x;
+        z[1] = t.y;
+        z[2] = t.z;
+        z[3] = t.w;
+      } else {
+        for (int j = 0; j < 4; ++j) z[j] = da[i + j];
+      }
+      if constexpr (FUSED) {
+        if (relu) {
+          uint16_t h[4];
+          if (vec) {
+            const uint2 w = *reinterpret_cast<const uint2*>(a + i);
+            h[0] = (uint16_t)w.x;
+            h[1] = (uint16_t)(w.x >> 16);
+            h[2] = (uint16_t)w.y;
+            h[3] = (uint16_t)(w.y >> 16);
+          } else {
+            for (int j = 0; j < 4; ++j) h[j] = a[i + j];
+          }
+          for (int j = 0; j < 4; ++j)
+            if (!(bf2f(h[j]) > 0.f)) z[j] = 0.f;
+        }
+        uint16_t o[4];
+        for (int j = 0; j < 4; ++j) o[j] = f2bf(z[j]);
+        if (vec)
+          *reinterpret_cast<uint2*>(dzb + i) =
+              make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+        else
+          for (int j = 0; j < 4; ++j) dzb[i + j] = o[j];
+      }
+      s.x += z[0];
+      s.y += z[1];
+      s.z += z[2];
+      s.w += z[3];
+    }
+  }
+  sh[tid] = s;
+  __syncthreads();
+  if (tid < c4) {
+    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r = 0; r < G; ++r) {
+      const float4 u = sh[r * c4 + tid];
+      t.x += u.x;
+      t.y += u.y;
+      t.z += u.z;
+      t.w += u.w;
+    }
+    float* out = part + (long long)blockIdx.x * c + 4 * tid;
+    out[0] = t.x;
+    out[1] = t.y;
+    out[2] = t.z;
+    out[3] = t.w;
+  }
+}
+bool bias4(int c) { return c % 4 == 0 && c <= 1024; }
+
 // The backward of a layer's activation, fused with what the convolution's
 // backward needs from it: dz = (relu ? (a > 0 ? da : 0) : da) stored as BF16
 // (the MFMA operand of both convolution gradients), and the first pass of
@@ -1219,8 +1306,12 @@ NN_API lbm_status nn_bias_grad(const float* dy, float* db, void* ws, size_t ws_b
   if (!ws || ws_bytes < need) return LBM_ERR_WORKSPACE;
   const long long splits = need / ((size_t)c * sizeof(float));
   const long long per = (m + splits - 1) / splits;
-  bias_grad_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(dy, (float*)ws, m, c,
-                                                                          per);
+  if (bias4(c))
+    bias4_part_kernel<false><<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(
+        dy, nullptr, nullptr, (float*)ws, m, c, per, 0, aligned16(dy) ? 1 : 0);
+  else
+    bias_grad_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(dy, (float*)ws, m,
+                                                                            c, per);
   fold_splits_kernel<<<grid_for(c), 256, 0, (hipStream_t)stream>>>((const float*)ws, db, c,
                                                                   (int)splits);
   return check_launch();
@@ -1236,8 +1327,14 @@ NN_API lbm_status nn_relu_backward_bias(const float* da, const void* a, void* dz
   if (!ws || ws_bytes < need) return LBM_ERR_WORKSPACE;
   const long long splits = need / ((size_t)c * sizeof(float));
   const long long per = (m + splits - 1) / splits;
-  relu_bwd_bias_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(
-      da, (const uint16_t*)a, (uint16_t*)dz, (float*)ws, m, c, per, relu);
+  if (bias4(c)) {
+    const bool vec = aligned16(da) && ((uintptr_t)dz & 7) == 0 && (!relu || ((uintptr_t)a & 7) == 0);
+    bias4_part_kernel<true><<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(
+        da, (const uint16_t*)a, (uint16_t*)dz, (float*)ws, m, c, per, relu, vec ? 1 : 0);
+  } else {
+    relu_bwd_bias_part_kernel<<<(unsigned)splits, 256, 0, (hipStream_t)stream>>>(
+        da, (const uint16_t*)a, (uint16_t*)dz, (float*)ws, m, c, per, relu);
+  }
   fold_splits_kernel<<<grid_for(c), 256, 0, (hipStream_t)stream>>>((const float*)ws, db, c,
                                                                   (int)splits);
   return check_launch();

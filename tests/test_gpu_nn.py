@@ -187,6 +187,43 @@ def test_relu_backward_bias_fused(ctx, m, c):
                                      m, c, 1, s) == 1  # ReLU without the activation
 
 
+def test_bias_grad_vector_and_scalar_accesses_agree(ctx):
+    """Four channels per thread: 16-byte FP32 and 8-byte BF16 accesses when
+    the pointers allow them, element accesses in the same order when they do
+    not (here: every pointer one element off alignment).  dz and db of the
+    fused and plain bias gradients are bit for bit the same either way."""
+    import ctypes as C
+
+    t = ctx.torch
+    m, c = 2000, 32
+    rng = np.random.default_rng(9)
+    lib = W._nn()
+    s = ctx.stream
+    da_h = rng.standard_normal((m, c)).astype(np.float32)
+    act_bits = _bf_dev(ctx, np.maximum(rng.standard_normal((m, c)), 0)).reshape(-1)
+    bb = C.c_size_t()
+    assert lib.nn_bias_grad_workspace(m, c, C.byref(bb)) == 0
+    ws = t.empty(bb.value, dtype=t.uint8, device=ctx.dev)
+    outs = []
+    for off in (0, 1):
+        da = t.zeros(m * c + 4, dtype=t.float32, device=ctx.dev)
+        da[off:off + m * c] = t.from_numpy(da_h.reshape(-1)).to(ctx.dev)
+        act = t.zeros(m * c + 4, dtype=act_bits.dtype, device=ctx.dev)
+        act[off:off + m * c] = act_bits
+        dz = t.zeros(m * c + 4, dtype=act_bits.dtype, device=ctx.dev)
+        db, db_plain = ctx.f32(c), ctx.f32(c)
+        pa, pact, pdz = (W._p(x[off:]) for x in (da, act, dz))
+        assert lib.nn_relu_backward_bias(pa, pact, pdz, W._p(db), W._p(ws), bb.value, m, c, 1,
+                                         s) == 0
+        assert lib.nn_bias_grad(pa, W._p(db_plain), W._p(ws), bb.value, m, c, s) == 0
+        t.cuda.synchronize()
+        outs.append((dz[off:off + m * c].clone(), db.clone(), db_plain.clone()))
+    (dz0, db0, dp0), (dz1, db1, dp1) = outs
+    assert t.equal(dz0.view(t.int16), dz1.view(t.int16))
+    assert t.equal(db0, db1) and t.equal(dp0, dp1)
+    assert rel(_host(dp0), da_h.astype(np.float64).sum(axis=0)) < 1e-5
+
+
 def test_mse_and_adam(ctx):
     rng = np.random.default_rng(4)
     lib = W._nn()
