@@ -97,6 +97,15 @@ lbm_status nn_pool2_forward(const void* x, void* y, int n, int d, int h, int w_,
 lbm_status nn_pool2_backward(const float* dy, float* dx, int n, int d, int h, int w_, int c,
                              void* stream);
 
+/* Periodic trilinear prolongation by 2 (the two-grid warm start): y (float,
+ * n,2d,2h,2w,c) from the first c of the cx channels of x (float, coarse
+ * n,d,h,w,cx; c <= cx).  Fine node i of an axis lies between coarse nodes,
+ * 3/4 from the nearer m = i/2 and 1/4 from the farther (m-1 for even i, m+1
+ * for odd i) and takes 0.75 x[m] + 0.25 x[far], axes z, y, x in turn; then
+ * y *= scale[ch] (device float[c], or NULL for 1). */
+lbm_status nn_prolongate2(const float* x, float* y, int n, int d, int h, int w_, int cx, int c,
+                          const float* scale, void* stream);
+
 /* Nearest-neighbour upsampling by 2 of x (bf16, coarse n,d,h,w,c) into y, and
  * its gradient (sum over the 8 children; dims are the coarse ones). */
 lbm_status nn_upsample2_forward(const void* x, void* y, int n, int d, int h, int w_, int c,

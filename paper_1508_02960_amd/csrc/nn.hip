@@ -1404,6 +1404,53 @@ NN_API lbm_status nn_pool2_backward(const float* dy, float* dx, int n, int d, in
   return check_launch();
 }
 
+// Periodic trilinear prolongation by 2 (the two-grid warm start): fine node
+// i of an axis sits between coarse nodes, 3/4 from the nearer one m = i / 2
+// and 1/4 from the farther (m - 1 for even i, m + 1 for odd i), so it takes
+// 0.75 x[m] + 0.25 x[far].  The three axes are applied in the order z, y, x,
+// then the channel scale.
+__global__ void prolong2_kernel(const float* __restrict__ x, float* __restrict__ y, int n, int d,
+                                int h, int w, int cx, int c, const float* __restrict__ scale,
+                                long long total) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
+    long long r = i / c;
+    const int X = (int)(r % (2 * w));
+    r /= 2 * w;
+    const int Y = (int)(r % (2 * h));
+    r /= 2 * h;
+    const int Z = (int)(r % (2 * d));
+    const int b = (int)(r / (2 * d));
+    const int xn = X >> 1, yn = Y >> 1, zn = Z >> 1;
+    const int xf = (X & 1) ? (xn + 1 == w ? 0 : xn + 1) : (xn == 0 ? w - 1 : xn - 1);
+    const int yf = (Y & 1) ? (yn + 1 == h ? 0 : yn + 1) : (yn == 0 ? h - 1 : yn - 1);
+    const int zf = (Z & 1) ? (zn + 1 == d ? 0 : zn + 1) : (zn == 0 ? d - 1 : zn - 1);
+    auto at = [&](int zz, int yy, int xx) {
+      return x[((((long long)b * d + zz) * h + yy) * w + xx) * cx + ch];
+    };
+    float a[2];  // the y-then-z interpolated values at the near and far x
+    for (int q = 0; q < 2; ++q) {
+      const int xx = q ? xf : xn;
+      const float bn = 0.75f * at(zn, yn, xx) + 0.25f * at(zf, yn, xx);
+      const float bf = 0.75f * at(zn, yf, xx) + 0.25f * at(zf, yf, xx);
+      a[q] = 0.75f * bn + 0.25f * bf;
+    }
+    const float v = 0.75f * a[0] + 0.25f * a[1];
+    y[i] = scale ? v * scale[ch] : v;
+  }
+}
+
+NN_API lbm_status nn_prolongate2(const float* x, float* y, int n, int d, int h, int w, int cx,
+                                 int c, const float* scale, void* stream) {
+  if (!x || !y || bad_shape(n, d, h, w) || cx < 1 || c < 1 || c > cx)
+    return LBM_ERR_INVALID_ARG;
+  const long long total = 8LL * n * d * h * w * c;
+  prolong2_kernel<<<grid_for(total), 256, 0, (hipStream_t)stream>>>(x, y, n, d, h, w, cx, c, scale,
+                                                                    total);
+  return check_launch();
+}
+
 NN_API lbm_status nn_upsample2_forward(const void* x, void* y, int n, int d, int h, int w, int c,
                                        void* stream) {
   if (!x || !y || bad_shape(n, d, h, w) || c < 1) return LBM_ERR_INVALID_ARG;

@@ -58,6 +58,7 @@ def _nn():
         "nn_concat_channels": [vp, vp, vp, i64, i32, i32, vp],
         "nn_split_channels": [vp, vp, vp, i64, i32, i32, vp],
         "nn_add": [vp, vp, i64, vp],
+        "nn_prolongate2": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp],
         "nn_masked_mse": [vp, vp, vp, vp, vp, i32, i64, i32, i32, f64, vp],
         "nn_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
     }
@@ -77,7 +78,7 @@ NN_EXPORTS = (
     "nn_activation_forward", "nn_relu_backward", "nn_relu_backward_bias", "nn_cast_bf16",
     "nn_pool2_forward",
     "nn_pool2_backward", "nn_upsample2_forward", "nn_upsample2_backward", "nn_concat_channels",
-    "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam",
+    "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam", "nn_prolongate2",
 )
 
 
@@ -486,6 +487,24 @@ def prolongate2(t: np.ndarray) -> np.ndarray:
     scale[:3] = 4.0
     scale[3:] = 2.0
     return (out * scale).astype(np.float32)
+
+
+def predict_two_grid(net, spheres, edge: int, used: int = 4) -> np.ndarray:
+    """Two-grid prediction of a pack of edge^3 (edge a multiple of 16): the
+    network on coarse_fluid's grid, then the prolongation of prolongate2 on
+    the device (nn_prolongate2, with the network's output scale and the
+    doubled lengths in the channel scale); target units, (edge,)*3 + (used,)."""
+    lib = _nn()
+    ctx = net.ctx
+    t = ctx.torch
+    ec = edge // 2
+    out = net.forward(network_input(ctx, coarse_fluid(spheres, edge)[None].astype(np.uint8)))
+    lengths = [4.0] * min(used, 3) + [2.0] * max(used - 3, 0)
+    scale = t.tensor([net.scale * s for s in lengths], dtype=t.float32, device=ctx.dev)
+    fine = ctx.f32(1, edge, edge, edge, used)
+    _chk(lib.nn_prolongate2(_p(out), _p(fine), 1, ec, ec, ec, int(out.shape[-1]), used, _p(scale),
+                            ctx.stream), "prolongate2")
+    return fine[0].cpu().numpy()
 
 
 _D3Q19_NEIGHBOURS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)

@@ -250,7 +250,7 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
     controls=False runs only the rest and network starts.  With two_grid
     each network also predicts on the half-resolution grid of every pack
     (warmstart.coarse_fluid), and the prediction interpolated back
-    (warmstart.prolongate2) is the start network_u_2grid[n]; direct=False
+    (warmstart.predict_two_grid) is the start network_u_2grid[n]; direct=False
     then leaves out the full-resolution starts."""
     if not isinstance(nets, dict):
         nets = {"": nets}
@@ -276,8 +276,7 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
                 starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
             if two_grid:
                 t0 = time.perf_counter()
-                pc = np.stack([W.prolongate2(net.predict(W.coarse_fluid(sp, edge)))
-                               for sp, _ in packs])
+                pc = np.stack([W.predict_two_grid(net, sp, edge) for sp, _ in packs])
                 out["predict_seconds_2grid" + tag] = time.perf_counter() - t0
                 preds["_2grid" + tag] = pc
                 wu = [W.warm_fields(pc[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]

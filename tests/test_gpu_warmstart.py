@@ -68,3 +68,40 @@ def test_warm_start_gains_over_rest(trained):
     assert np.median(np.array(warm[0]) / np.array(rest[0])) < 0.3
     # ... and reaches 0.1 % of it in fewer steps
     assert np.median(s_warm / s_rest) < 1.0
+
+
+def test_prolongate2_kernel_matches_host():
+    """nn_prolongate2 (two batch entries, the first 4 of 8 channels, a channel
+    scale) against warmstart.prolongate2, whose linear exactness and length
+    scaling the host tests pin."""
+    import torch
+
+    lib = W._nn()
+    ctx = W._Ctx("cuda")
+    rng = np.random.default_rng(21)
+    n, d, h, w, cx, c = 2, 4, 6, 8, 8, 4
+    x = rng.standard_normal((n, d, h, w, cx)).astype(np.float32)
+    xd = torch.from_numpy(x).to(ctx.dev)
+    y = ctx.f32(n, 2 * d, 2 * h, 2 * w, c)
+    scale = torch.tensor([4.0, 4.0, 4.0, 2.0], dtype=torch.float32, device=ctx.dev)
+    assert lib.nn_prolongate2(W._p(xd), W._p(y), n, d, h, w, cx, c, W._p(scale), ctx.stream) == 0
+    got = y.cpu().numpy()
+    for b in range(n):
+        want = W.prolongate2(x[b, ..., :c])
+        assert np.max(np.abs(got[b] - want)) <= 1e-6 * np.max(np.abs(want))
+    y1 = ctx.f32(n, 2 * d, 2 * h, 2 * w, 1)
+    assert lib.nn_prolongate2(W._p(xd), W._p(y1), n, d, h, w, cx, 1, None, ctx.stream) == 0
+    want1 = W.prolongate2(x[0, ..., :4])[..., 0] / 4.0
+    assert np.max(np.abs(y1.cpu().numpy()[0, ..., 0] - want1)) <= 1e-6 * np.max(np.abs(want1))
+    assert lib.nn_prolongate2(W._p(xd), W._p(y), n, d, h, w, cx, cx + 1, None, ctx.stream) != 0
+
+
+def test_two_grid_prediction_on_the_device(trained):
+    """predict_two_grid (network and prolongation on the device) equals the
+    host composition prolongate2(predict(coarse_fluid)) to FP32 rounding."""
+    net = trained[0] if isinstance(trained, tuple) else trained
+    sp = S.draw_packs(1, 32, 9, (8, 12))[0][0]
+    got = W.predict_two_grid(net, sp, 32)
+    want = W.prolongate2(net.predict(W.coarse_fluid(sp, 32)))
+    assert got.shape == want.shape == (32, 32, 32, 4)
+    assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))
