@@ -159,7 +159,8 @@ def warm_start_leg(n_cells: int):
     on 64^3 packs of 8-27 spheres; it predicts each 128^3 pack on the grid of
     half the resolution (its receptive field then spans the cell) and the
     prediction is interpolated back (two-grid start).  The warm start's time
-    includes the inference."""
+    includes building the start on the device: coarse masks, network,
+    prolongation and start fields (warm_setup_s)."""
     from paper_1508_02960_amd import warmstart, warmstart_study
 
     weights = os.path.join(ROOT, "paper_1508_02960_amd", "data", "unet64_dense_bf16.npz")
@@ -175,7 +176,7 @@ def warm_start_leg(n_cells: int):
                     "start from the network trained on 64^3 packs of 8-27 spheres",
         "plain_s": round(plain["seconds"], 3),
         "warm_s": round(warm["seconds"] + r["predict_seconds_2grid"], 3),
-        "inference_s": round(r["predict_seconds_2grid"], 3),
+        "warm_setup_s": round(r["predict_seconds_2grid"], 3),
         "plain_steps_median": float(np.median(plain["steps"])),
         "warm_steps_median": float(np.median(warm["steps"])),
         "step_ratio_median": round(warm["step_ratio_median"], 4),

@@ -106,6 +106,19 @@ lbm_status nn_pool2_backward(const float* dy, float* dx, int n, int d, int h, in
 lbm_status nn_prolongate2(const float* x, float* y, int n, int d, int h, int w_, int cx, int c,
                           const float* scale, void* stream);
 
+/* Start fields of a warm start for lbm_init_equilibrium_device, from the
+ * predicted targets t (float, n,d,h,w,cx; velocity targets in channels 0-2,
+ * cx >= 3) and the fluid mask (uint8, n,d,h,w; nonzero = fluid).  fields
+ * (device double[4*n*d*h*w], [drho | u_x | u_y | u_z] in cell order, the
+ * boxes stacked along z as in a batch): drho = -(delta_rho/w)(x - (w-1)/2)
+ * on fluid cells (the linear profile of the pressure drop across x); u =
+ * factor * t on fluid cells none of whose 18 lattice neighbours (periodic
+ * within the box) is solid, else 0 (a velocity imposed on the wall layer
+ * excites slowly decaying oscillations of the bounce-back links). */
+lbm_status nn_warm_start_fields(const float* t, int cx, const void* fluid, double* fields, int n,
+                                int d, int h, int w_, double factor, double delta_rho,
+                                void* stream);
+
 /* Nearest-neighbour upsampling by 2 of x (bf16, coarse n,d,h,w,c) into y, and
  * its gradient (sum over the 8 children; dims are the coarse ones). */
 lbm_status nn_upsample2_forward(const void* x, void* y, int n, int d, int h, int w_, int c,

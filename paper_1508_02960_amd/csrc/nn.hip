@@ -1451,6 +1451,51 @@ NN_API lbm_status nn_prolongate2(const float* x, float* y, int n, int d, int h, 
   return check_launch();
 }
 
+// Start fields of a warm start, for lbm_init_equilibrium_device, from
+// predicted targets t (n boxes of d x h x w, cx channels; velocity targets in
+// channels 0-2) and the fluid mask: drho = -(delta_rho / w)(x - (w - 1)/2) on
+// fluid cells (the linear profile of the pressure drop), u = factor * t on
+// fluid cells none of whose 18 lattice neighbours (periodic in the box) is
+// solid, 0 elsewhere.  fields: [drho | u_x | u_y | u_z], n d h w values each.
+__global__ void warm_fields_kernel(const float* __restrict__ t, int cx,
+                                   const uint8_t* __restrict__ fluid, double* __restrict__ fields,
+                                   int n, int d, int h, int w, double factor, double delta_rho) {
+  const long long total = (long long)n * d * h * w;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % w);
+    long long r = i / w;
+    const int y = (int)(r % h);
+    r /= h;
+    const int z = (int)(r % d);
+    const long long box = (r / d) * (long long)d * h * w;
+    const bool f = fluid[i] != 0;
+    bool wall = false;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int a = (dz != 0) + (dy != 0) + (dx != 0);
+          if (a == 0 || a == 3) continue;  // the 18 moving D3Q19 directions
+          const int zz = (z + dz + d) % d, yy = (y + dy + h) % h, xx = (x + dx + w) % w;
+          wall |= fluid[box + ((long long)zz * h + yy) * w + xx] == 0;
+        }
+    const double xc = x - (w - 1) / 2.0;
+    fields[i] = f ? -(delta_rho / w) * xc : 0.0;
+    for (int k = 0; k < 3; ++k)
+      fields[(1 + k) * total + i] = (f && !wall) ? (double)t[i * cx + k] * factor : 0.0;
+  }
+}
+
+NN_API lbm_status nn_warm_start_fields(const float* t, int cx, const void* fluid, double* fields,
+                                       int n, int d, int h, int w, double factor,
+                                       double delta_rho, void* stream) {
+  if (!t || !fluid || !fields || bad_shape(n, d, h, w) || cx < 3) return LBM_ERR_INVALID_ARG;
+  const long long total = (long long)n * d * h * w;
+  warm_fields_kernel<<<grid_for(total), 256, 0, (hipStream_t)stream>>>(
+      t, cx, (const uint8_t*)fluid, fields, n, d, h, w, factor, delta_rho);
+  return check_launch();
+}
+
 NN_API lbm_status nn_upsample2_forward(const void* x, void* y, int n, int d, int h, int w, int c,
                                        void* stream) {
   if (!x || !y || bad_shape(n, d, h, w) || c < 1) return LBM_ERR_INVALID_ARG;

@@ -59,6 +59,7 @@ def _nn():
         "nn_split_channels": [vp, vp, vp, i64, i32, i32, vp],
         "nn_add": [vp, vp, i64, vp],
         "nn_prolongate2": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp],
+        "nn_warm_start_fields": [vp, i32, vp, vp, i32, i32, i32, i32, f64, f64, vp],
         "nn_masked_mse": [vp, vp, vp, vp, vp, i32, i64, i32, i32, f64, vp],
         "nn_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
     }
@@ -79,6 +80,7 @@ NN_EXPORTS = (
     "nn_pool2_forward",
     "nn_pool2_backward", "nn_upsample2_forward", "nn_upsample2_backward", "nn_concat_channels",
     "nn_split_channels", "nn_add", "nn_masked_mse", "nn_adam", "nn_prolongate2",
+    "nn_warm_start_fields",
 )
 
 
@@ -489,22 +491,48 @@ def prolongate2(t: np.ndarray) -> np.ndarray:
     return (out * scale).astype(np.float32)
 
 
-def predict_two_grid(net, spheres, edge: int, used: int = 4) -> np.ndarray:
+def predict_two_grid_device(net, spheres, edge: int, out=None, used: int = 4):
     """Two-grid prediction of a pack of edge^3 (edge a multiple of 16): the
     network on coarse_fluid's grid, then the prolongation of prolongate2 on
     the device (nn_prolongate2, with the network's output scale and the
-    doubled lengths in the channel scale); target units, (edge,)*3 + (used,)."""
+    doubled lengths in the channel scale); target units, a device tensor
+    (edge,)*3 + (used,), written into out if given."""
     lib = _nn()
     ctx = net.ctx
     t = ctx.torch
     ec = edge // 2
-    out = net.forward(network_input(ctx, coarse_fluid(spheres, edge)[None].astype(np.uint8)))
+    y = net.forward(network_input(ctx, coarse_fluid(spheres, edge)[None].astype(np.uint8)))
     lengths = [4.0] * min(used, 3) + [2.0] * max(used - 3, 0)
     scale = t.tensor([net.scale * s for s in lengths], dtype=t.float32, device=ctx.dev)
-    fine = ctx.f32(1, edge, edge, edge, used)
-    _chk(lib.nn_prolongate2(_p(out), _p(fine), 1, ec, ec, ec, int(out.shape[-1]), used, _p(scale),
+    fine = out if out is not None else ctx.f32(edge, edge, edge, used)
+    _chk(lib.nn_prolongate2(_p(y), _p(fine), 1, ec, ec, ec, int(y.shape[-1]), used, _p(scale),
                             ctx.stream), "prolongate2")
-    return fine[0].cpu().numpy()
+    return fine
+
+
+def predict_two_grid(net, spheres, edge: int, used: int = 4) -> np.ndarray:
+    """predict_two_grid_device on the host."""
+    return predict_two_grid_device(net, spheres, edge, used=used).cpu().numpy()
+
+
+def warm_fields_device(ctx, t, fluid, delta_rho: float, tau: float):
+    """warm_fields on the device (nn_warm_start_fields): t the predicted
+    targets (n, d, h, w, c) on the device, fluid the host masks (n, d, h, w);
+    returns the (4, n d h w) float64 device fields of
+    Batch.init_equilibrium_device (the linear density, the predicted velocity
+    away from walls)."""
+    lib = _nn()
+    th = ctx.torch
+    n, d, h, w = fluid.shape
+    if (tuple(t.shape[:-1]) != (n, d, h, w) or t.shape[-1] < 3 or t.dtype != th.float32
+            or not t.is_contiguous() or not t.is_cuda):
+        raise ValueError(f"targets {tuple(t.shape)} do not match the masks {fluid.shape}")
+    f = th.from_numpy(np.ascontiguousarray(fluid, np.uint8)).to(ctx.dev)
+    fields = th.empty((4, n * d * h * w), dtype=th.float64, device=ctx.dev)
+    factor = observables.pressure_gradient(delta_rho, w) / observables.viscosity(tau)
+    _chk(lib.nn_warm_start_fields(_p(t), int(t.shape[-1]), _p(f), _p(fields), n, d, h, w,
+                                  float(factor), float(delta_rho), ctx.stream), "warm fields")
+    return fields
 
 
 _D3Q19_NEIGHBOURS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)

@@ -223,10 +223,25 @@ def _run(b, tol, max_steps, log, name):
     return out
 
 
+class _DeviceStart:
+    """Start fields already on the device (Batch.init_equilibrium_device)."""
+
+    def __init__(self, fields):
+        self.fields = fields
+
+
+def _init(b, start):
+    """Initialise the batch from a start: host (drho, u) or _DeviceStart."""
+    if isinstance(start, _DeviceStart):
+        b.init_equilibrium_device(start.fields)
+    else:
+        b.init_equilibrium(*start)
+
+
 def _trajectory(b, start, chunk, n_chunks):
     """Per-cell U_x after each of n_chunks runs of chunk steps from start
     (tolerance 0, so every cell runs the full chunk)."""
-    b.init_equilibrium(*start)
+    _init(b, start)
     traj = []
     for _ in range(n_chunks):
         b.run_to_residual(0.0, chunk)
@@ -275,12 +290,18 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
                       for i in range(len(packs))]
                 starts["network_u" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
             if two_grid:
+                # the whole start on the device, timed: coarse masks, network,
+                # prolongation and the start fields
+                ctx = net.ctx
                 t0 = time.perf_counter()
-                pc = np.stack([W.predict_two_grid(net, sp, edge) for sp, _ in packs])
+                fine = ctx.f32(len(packs), edge, edge, edge, 4)
+                for i, (sp, _) in enumerate(packs):
+                    W.predict_two_grid_device(net, sp, edge, out=fine[i])
+                fields = W.warm_fields_device(ctx, fine, fluid, delta_rho, tau)
+                ctx.torch.cuda.synchronize()
                 out["predict_seconds_2grid" + tag] = time.perf_counter() - t0
-                preds["_2grid" + tag] = pc
-                wu = [W.warm_fields(pc[i], delta_rho, tau, fluid[i]) for i in range(len(packs))]
-                starts["network_u_2grid" + tag] = (lin, np.stack([w[1] for w in wu], axis=1))
+                preds["_2grid" + tag] = fine.cpu().numpy()
+                starts["network_u_2grid" + tag] = _DeviceStart(fields)
             if with_density and tag in preds:
                 wr = [W.warm_fields(preds[tag][i], delta_rho, tau, fluid[i], use_density=True)
                       for i in range(len(packs))]
@@ -291,7 +312,7 @@ def evaluate(nets, packs, edge: int, *, tau: float, delta_rho: float, tol: float
         for name, start in list(starts.items()) + extra:
             if name == "converged_fields":
                 start = conv
-            b.init_equilibrium(*start)
+            _init(b, start)
             out[name] = _run(b, tol, max_steps, log, name)
             if name == "rest":
                 drho, u = b.macroscopic()

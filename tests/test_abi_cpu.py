@@ -32,7 +32,7 @@ def test_library_exports_every_network_function():
 
     lib = warmstart._nn()
     names = _header_functions("lbm_nn.h", "nn_")
-    assert len(names) == 22
+    assert len(names) == 23
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(warmstart.NN_EXPORTS)

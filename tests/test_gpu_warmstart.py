@@ -5,6 +5,7 @@ The warm start must need fewer steps and reach the same permeability."""
 import numpy as np
 import pytest
 
+from paper_1508_02960_amd import inputs
 from paper_1508_02960_amd import warmstart as W
 from paper_1508_02960_amd import warmstart_study as S
 
@@ -105,3 +106,29 @@ def test_two_grid_prediction_on_the_device(trained):
     want = W.prolongate2(net.predict(W.coarse_fluid(sp, 32)))
     assert got.shape == want.shape == (32, 32, 32, 4)
     assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))
+
+
+def test_warm_start_fields_kernel_matches_host():
+    """nn_warm_start_fields (two periodic packs, a ragged box, 4 target
+    channels of which the velocity uses 3) against warmstart.warm_fields:
+    the linear density on fluid nodes and the scaled predicted velocity away
+    from the wall layer, bit for bit (the same FP64 products)."""
+    import torch
+
+    ctx = W._Ctx("cuda")
+    rng = np.random.default_rng(23)
+    shape = (2, 6, 9, 11)
+    fluid = np.stack([inputs.random_mask(shape[1:], 0.05, seed=60 + i) == 0
+                      for i in range(shape[0])])
+    assert 0 < fluid.mean() < 1
+    t = rng.standard_normal(shape + (4,)).astype(np.float32)
+    delta_rho, tau = 3e-3, 0.8
+    fields = W.warm_fields_device(ctx, torch.from_numpy(t).to(ctx.dev), fluid, delta_rho, tau)
+    got = fields.cpu().numpy().reshape((4,) + shape)
+    assert 0 < np.count_nonzero(got[1]) < fluid.sum()  # some nodes away from walls, not all
+    for b in range(shape[0]):
+        drho, u = W.warm_fields(t[b], delta_rho, tau, fluid[b])
+        assert np.array_equal(got[0, b], drho)
+        assert np.array_equal(got[1:, b], u)
+    with pytest.raises(ValueError):
+        W.warm_fields_device(ctx, torch.from_numpy(t[:1]).to(ctx.dev), fluid, delta_rho, tau)
