@@ -205,15 +205,17 @@ def test_batch_autotune_and_unstable_cell():
 def test_full_batch_configuration_sampled_cells(orc):
     """The full 256-cell batch of 64^3 cells (one sphere of D in [40, 60] at a
     random centre, tau in [0.55, 1], seed 4, as the batch study draws them),
-    FP32, autotuned launch shape, 40 steps from rest under per-cell pressure
-    drops; sampled cells (first, middle, last) against the FP64 oracle run on
-    that cell alone: velocity within 1e-5."""
+    FP32 in 8 x 8 tiles (a state beyond 1 GiB), autotuned launch shape, 40
+    steps from rest under per-cell pressure drops; sampled cells (first,
+    middle, last) against the FP64 oracle run on that cell alone: velocity
+    within 1e-5."""
     from paper_1508_02960_amd import batch_study
 
     draws, _ = batch_study.draw_cells(256, 4, 64)
     cells = [dict(spheres=c["spheres"], tau=c["tau"], magic=3 / 16,
                   delta_rho=1e-4 * (1 + (i % 7))) for i, c in enumerate(draws)]
     b = lbm.Batch((64, 64, 64), cells, wall="cli", storage="fp32")
+    assert (b.info.tile_width, b.info.tile_height) == (8, 8)
     b.autotune(steps=3)
     b.init_equilibrium()
     b.step(40)
