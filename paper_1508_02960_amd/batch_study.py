@@ -9,6 +9,7 @@ the main run goes to a 1e-8 relative velocity residual with a per-cell step
 cap, after the launch shape is autotuned.
 
     python -m paper_1508_02960_amd.batch_study --out batch.json
+    python -m paper_1508_02960_amd.batch_study --speed 100   # step timing only
 """
 from __future__ import annotations
 
@@ -93,6 +94,36 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     return out
 
 
+def speed(n_cells=256, edge=64, seed=4, steps=100, shape=None, log=print, device=None):
+    """The study's batch under its Stokes forcing, stepped `steps` times from
+    rest with every cell running: ms per step of all cells.  shape =
+    (wavefronts per block, z planes per block, solid-write mode) fixes the
+    launch (then the only step launches are the timed ones, as a profiler
+    should see them); by default the autotuner chooses it."""
+    cells, _ = draw_cells(n_cells, seed, edge)
+    b = lbm.Batch((edge, edge, edge), [dict(c, delta_rho=1e-7) for c in cells], wall="cli",
+                  storage="fp32", device=device)
+    if shape:
+        by, zp, mode = shape
+        b.set_shape(by, zp)
+        b.set_solid_writes(mode)
+    else:
+        by, zp, _ = b.autotune(steps=5)
+    b.init_equilibrium()
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    out = dict(n_cells=n_cells, edge=edge, n_fluid=int(b.info.n_fluid), waves_per_block=by,
+               z_planes_per_block=zp, solid_writes=b.solid_writes,
+               tile=[b.info.tile_width, b.info.tile_height], steps=steps, ms_per_step=ms,
+               mflups=b.info.n_fluid / ms / 1e3)
+    b.close()
+    log(f"[batch] {steps} steps of all cells: {ms:.4f} ms per step, {out['mflups']:.0f} MFLUPS")
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--cells", type=int, default=256)
@@ -100,8 +131,16 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--max-steps", type=int, default=200000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--speed", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS steps of the batch from rest")
+    ap.add_argument("--shape", type=int, nargs=3, default=None, metavar=("WAVES", "ZPER", "MODE"),
+                    help="launch shape for --speed (default: autotuned)")
     a = ap.parse_args(argv)
-    res = run(a.cells, a.edge, a.seed, max_steps=a.max_steps, log=lambda s: print(s, flush=True))
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if a.speed > 0:
+        res = speed(a.cells, a.edge, a.seed, a.speed, shape=a.shape, log=log)
+    else:
+        res = run(a.cells, a.edge, a.seed, max_steps=a.max_steps, log=log)
     txt = json.dumps(res)
     if a.out:
         open(a.out, "w").write(txt)

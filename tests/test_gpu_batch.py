@@ -231,3 +231,13 @@ def test_full_batch_configuration_sampled_cells(orc):
         fluid = o.mask == 0
         err = np.max(np.abs(u[:, i][:, fluid] - uo[:, fluid])) / np.max(np.abs(uo[:, fluid]))
         assert err < 1e-5, (i, err)
+
+
+def test_batch_speed_mode():
+    """batch_study.speed (the timing run behind the batch step's profile):
+    two cells of the study at a fixed launch shape, every cell running."""
+    from paper_1508_02960_amd import batch_study
+
+    r = batch_study.speed(n_cells=2, edge=64, seed=4, steps=4, shape=(4, 1, 2), log=lambda s: None)
+    assert (r["waves_per_block"], r["z_planes_per_block"], r["solid_writes"]) == (4, 1, 2)
+    assert r["n_fluid"] > 0 and r["ms_per_step"] > 0 and r["mflups"] > 0
