@@ -244,8 +244,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the step would shard by z slabs with halo exchange); run with --gpus 1.",
               file=sys.stderr)
         return 2
 

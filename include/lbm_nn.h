@@ -3,7 +3,7 @@
  *
  * The network maps a solid mask to an initial velocity field that starts the
  * lattice Boltzmann iteration closer to its steady state; the plain iteration
- * run to the residual tolerance remains the judge of the result.  These entry
+ * run to the residual tolerance still decides the result.  These entry
  * points are its layers, each a HIP kernel on gfx950: 3x3x3 convolutions as
  * implicit GEMMs on BF16 matrix cores (v_mfma_f32_16x16x32_bf16) with FP32
  * accumulation, and the pooling, upsampling, activation, loss and optimiser
