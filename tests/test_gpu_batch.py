@@ -241,3 +241,31 @@ def test_batch_speed_mode():
     r = batch_study.speed(n_cells=2, edge=64, seed=4, steps=4, shape=(4, 1, 2), log=lambda s: None)
     assert (r["waves_per_block"], r["z_planes_per_block"], r["solid_writes"]) == (4, 1, 2)
     assert r["n_fluid"] > 0 and r["ms_per_step"] > 0 and r["mflups"] > 0
+
+
+def test_fp64_batch_in_large_tiles_matches_oracle(orc):
+    """An FP64 batch beyond 1 GiB (16 cells of 64^3 of the batch study, so
+    8 x 8 tiles and streaming stores), 20 steps from a random state under
+    per-cell pressure drops: the first and last cells against the FP64
+    oracle run on that cell alone, within 1e-12 of the largest population."""
+    from paper_1508_02960_amd import batch_study
+
+    draws, _ = batch_study.draw_cells(16, 4, 64)
+    cells = [dict(spheres=c["spheres"], tau=c["tau"], magic=3 / 16,
+                  delta_rho=1e-4 * (1 + (i % 5))) for i, c in enumerate(draws)]
+    b = lbm.Batch((64, 64, 64), cells, wall="cli", storage="fp64")
+    assert (b.info.tile_width, b.info.tile_height) == (8, 8)
+    g0 = inputs.random_populations((16, 64, 64, 64), 1e-3, seed=70)
+    b.set_state(g0)
+    b.step(20)
+    g = b.get_state()
+    b.close()
+    for i in (0, 15):
+        c = cells[i]
+        o = orc.Oracle((64, 64, 64), tau=c["tau"], magic=c["magic"], delta_rho=c["delta_rho"],
+                       collision="trt", wall="cli", spheres=c["spheres"])
+        o.set_state(np.ascontiguousarray(g0[:, i]))
+        o.step(20)
+        fluid = o.mask == 0
+        err = np.max(np.abs(g[:, i][:, fluid] - o.g[:, fluid])) / np.max(np.abs(o.g[:, fluid]))
+        assert err < 1e-12, (i, err)
