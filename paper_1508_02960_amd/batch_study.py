@@ -94,15 +94,23 @@ def run(n_cells=256, edge=64, seed=4, tol=1e-8, max_steps=200000, check_interval
     return out
 
 
-def speed(n_cells=256, edge=64, seed=4, steps=100, shape=None, log=print, device=None):
-    """The study's batch under its Stokes forcing, stepped `steps` times from
-    rest with every cell running: ms per step of all cells.  shape =
+def speed(n_cells=256, edge=64, seed=4, steps=100, shape=None, packs=False, log=print,
+          device=None):
+    """The study's batch under its Stokes forcing (or, with packs, the
+    warm-start benchmark's random packs of 8-27 spheres at tau 0.8, seed 5),
+    stepped `steps` times from rest with every cell running: ms per step of
+    all cells.  shape =
     (wavefronts per block, z planes per block, solid-write mode) fixes the
     launch (then the only step launches are the timed ones, as a profiler
     should see them); by default the autotuner chooses it."""
-    cells, _ = draw_cells(n_cells, seed, edge)
-    b = lbm.Batch((edge, edge, edge), [dict(c, delta_rho=1e-7) for c in cells], wall="cli",
-                  storage="fp32", device=device)
+    if packs:
+        from . import warmstart_study
+
+        drawn = warmstart_study.draw_packs(n_cells, edge, 5, warmstart_study.EVAL_SPHERES)
+        cells = [dict(spheres=sp, tau=0.8, magic=3 / 16, delta_rho=1e-5) for sp, _ in drawn]
+    else:
+        cells = [dict(c, delta_rho=1e-7) for c in draw_cells(n_cells, seed, edge)[0]]
+    b = lbm.Batch((edge, edge, edge), cells, wall="cli", storage="fp32", device=device)
     if shape:
         by, zp, mode = shape
         b.set_shape(by, zp)
@@ -135,10 +143,12 @@ def main(argv=None) -> int:
                     help="only time STEPS steps of the batch from rest")
     ap.add_argument("--shape", type=int, nargs=3, default=None, metavar=("WAVES", "ZPER", "MODE"),
                     help="launch shape for --speed (default: autotuned)")
+    ap.add_argument("--packs", action="store_true",
+                    help="--speed on the warm-start benchmark's packs of 8-27 spheres")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     if a.speed > 0:
-        res = speed(a.cells, a.edge, a.seed, a.speed, shape=a.shape, log=log)
+        res = speed(a.cells, a.edge, a.seed, a.speed, shape=a.shape, packs=a.packs, log=log)
     else:
         res = run(a.cells, a.edge, a.seed, max_steps=a.max_steps, log=log)
     txt = json.dumps(res)

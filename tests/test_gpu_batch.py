@@ -241,6 +241,9 @@ def test_batch_speed_mode():
     r = batch_study.speed(n_cells=2, edge=64, seed=4, steps=4, shape=(4, 1, 2), log=lambda s: None)
     assert (r["waves_per_block"], r["z_planes_per_block"], r["solid_writes"]) == (4, 1, 2)
     assert r["n_fluid"] > 0 and r["ms_per_step"] > 0 and r["mflups"] > 0
+    r = batch_study.speed(n_cells=1, edge=128, steps=2, shape=(2, 1, 2), packs=True,
+                          log=lambda s: None)
+    assert r["n_fluid"] > 0 and r["tile"] == [64, 1]  # one pack: 0.3 GB, rows of 64
 
 
 def test_fp64_batch_in_large_tiles_matches_oracle(orc):
